@@ -1,0 +1,153 @@
+/*
+ * steiner.h -- C ABI of the MI355X (gfx950) Voronoi-cell 2-approximation
+ * Steiner tree library.
+ *
+ * The method is the one of Reza, Sanders and Pearce, "Towards Distributed
+ * 2-Approximation Steiner Minimal Trees in Billion-edge Graphs"
+ * (arXiv:2205.14503), Alg. 2: Voronoi cells of the seeds (Step 1), the
+ * distance graph G'1 of minimum cross-cell edges (Step 2, Mehlhorn's
+ * construction, Section II), its MST (Step 3), pruning to the MST's cross-cell
+ * edges (Step 4), predecessor walks to the seeds (Steps 5-6) and the total
+ * distance D (Step 7).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns an int: STEINER_OK (0) or a negative STEINER_E* code.
+ *    Output parameters are written only on success.  steiner_last_error()
+ *    returns a thread-local string describing the most recent failure.
+ *  - Graphs are undirected, given as a symmetric CSR: row_ptr[n+1] (uint64),
+ *    col[nnz] and w[nnz] (uint32).  Rows must be sorted by column.  Weights
+ *    must be >= 1 (Table II: distances are positive integers).  Self-loops are
+ *    accepted and never used; parallel edges are accepted.  nnz must be below
+ *    2^32 because an edge is identified by its CSR offset.
+ *  - Seeds are vertex ids < n; duplicates are ignored.  Seed index i is the
+ *    rank of a seed in the sorted, deduplicated seed list.
+ *  - Results are exact and unique under these tie rules (the paper leaves
+ *    ties open): a vertex joins the cell minimising (distance, seed index);
+ *    pred(v) is the smallest in-cell neighbour on a shortest path (then the
+ *    smallest CSR offset); each cell pair keeps the cross-cell edge minimising
+ *    (d1(s,u)+d(u,v)+d1(v,t), edge id), the edge id being the CSR offset of the
+ *    half edge leaving the smaller endpoint; the MST of G'1 is the unique one
+ *    under the order (d'1, i, j).  No option changes any result.
+ *  - EOVERFLOW: some finite distance is >= 2^32-1, or some cross-cell sum
+ *    d1+d+d1 is >= 2^32.  EDISCONNECTED: the seeds do not lie in one
+ *    connected component.  k == 1 after deduplication gives an empty tree,
+ *    D = 0, without running any kernel.
+ *  - All device work of a graph runs on the HIP stream given at upload and
+ *    on the device given at upload.  Calls on one graph are serialised by the
+ *    library; distinct graphs are independent.
+ */
+#ifndef STEINER_H
+#define STEINER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    STEINER_OK = 0,
+    STEINER_EINVAL = -1,        /* malformed graph, seeds, sizes or options */
+    STEINER_ENOMEM = -2,        /* device or host allocation failed, or a caller buffer is too small */
+    STEINER_EDISCONNECTED = -3, /* seeds span more than one connected component */
+    STEINER_EOVERFLOW = -4,     /* a distance or cross-cell sum does not fit (see above) */
+    STEINER_EDEVICE = -5,       /* a HIP call failed */
+    STEINER_ETIMEDOUT = -6,     /* steiner_server_wait ran out of time */
+    STEINER_ECANCELED = -7      /* the server was destroyed before the request finished */
+};
+
+typedef struct steiner_graph steiner_graph;   /* device-resident CSR; owned by the library */
+typedef struct steiner_result steiner_result; /* host arrays of one tree; freed by steiner_result_free */
+typedef struct steiner_server steiner_server; /* continuous-batching query server over one graph */
+
+/* Execution knobs.  Pass NULL for defaults.  None of them changes any result. */
+typedef struct steiner_options {
+    uint32_t delta;       /* bucket width of the distance-ordered relaxation; 0 = default for the graph,
+                             0xFFFFFFFF = one unbounded bucket (plain label correcting) */
+    uint32_t driver;      /* 0 = default, 1 = host-stepped rounds, 2 = one persistent cooperative kernel */
+    uint32_t block;       /* threads per workgroup (multiple of 64, <= 1024); 0 = default */
+    uint32_t grid;        /* workgroups of the relaxation pass; 0 = default */
+    uint32_t small_max;   /* rows up to this degree are expanded wave-cooperatively; 0 = default */
+    uint32_t chunk;       /* larger rows are split into chunks of this many edges; 0 = default */
+    uint32_t flags;       /* STEINER_FLAG_* */
+    uint32_t reserved;
+} steiner_options;
+
+#define STEINER_FLAG_TIMING 1u /* record per-phase device times (adds synchronisation) */
+
+/* Per-solve statistics (filled for steiner_solve / steiner_solve_batch results). */
+typedef struct steiner_stats {
+    uint32_t rounds;          /* relaxation rounds executed */
+    uint32_t advances;        /* bucket advances (summed over queries) */
+    uint32_t pairs;           /* entries of G'1 (cell pairs joined by a cross-cell edge) */
+    uint32_t tree_edges;      /* |E_S| */
+    double ms_init, ms_voronoi, ms_scan, ms_compact, ms_mst, ms_expand, ms_total; /* device/host phase times */
+} steiner_stats;
+
+/* Upload a graph from HOST arrays (copied; the caller keeps ownership).
+ * device: HIP device ordinal.  hip_stream: a hipStream_t on that device, or
+ * NULL for the null stream.  flags: bit 0 = also verify symmetry (O(nnz)).
+ * EINVAL for n == 0, non-monotone row_ptr, row_ptr[0] != 0, row_ptr[n] != nnz,
+ * nnz >= 2^32, col >= n, w == 0, unsorted rows, or (flag 1) asymmetry. */
+int steiner_graph_upload(uint32_t n, uint64_t nnz, const uint64_t *row_ptr, const uint32_t *col,
+                         const uint32_t *w, int device, void *hip_stream, uint32_t flags, steiner_graph **out);
+
+/* Same, from DEVICE arrays on `device` (e.g. torch tensors); the library copies
+ * them into its own layout and validates them on the device. */
+int steiner_graph_upload_device(uint32_t n, uint64_t nnz, const void *d_row_ptr, const void *d_col,
+                                const void *d_w, int device, void *hip_stream, uint32_t flags,
+                                steiner_graph **out);
+
+int steiner_graph_free(steiner_graph *g);
+
+/* Alg. 2 end to end for one seed set (host array of k vertex ids). */
+int steiner_solve(steiner_graph *g, const uint32_t *seeds, uint32_t k, const steiner_options *opt,
+                  steiner_result **out);
+
+/* q seed sets solved in one multi-query pass over the shared graph.
+ * seeds[i] points to ks[i] host vertex ids.  outs[i] receives a result when
+ * status[i] == STEINER_OK.  Returns STEINER_OK if the pass itself ran (check
+ * status[] per query), or an error for the whole call. */
+int steiner_solve_batch(steiner_graph *g, uint32_t q, const uint32_t *const *seeds, const uint32_t *ks,
+                        const steiner_options *opt, steiner_result **outs, int *status);
+
+/* Tree edges (a < b, sorted by (a, b, w)); pointers stay valid until
+ * steiner_result_free. */
+int steiner_result_edges(const steiner_result *r, uint64_t *m, const uint32_t **a, const uint32_t **b,
+                         const uint32_t **w);
+uint64_t steiner_result_total(const steiner_result *r); /* D(G_S) */
+int steiner_result_stats(const steiner_result *r, steiner_stats *out);
+void steiner_result_free(steiner_result *r);
+
+/* Step 1 only: key_out[v] = (d1(src(v), v) << 32) | seed index, all ones when
+ * unreached; pred_out[v] = canonical predecessor (seed: itself; unreached:
+ * 0xFFFFFFFF).  Host arrays of n entries.  k must be >= 2 after deduplication. */
+int steiner_voronoi(steiner_graph *g, const uint32_t *seeds, uint32_t k, const steiner_options *opt,
+                    uint64_t *key_out, uint32_t *pred_out);
+
+/* Steps 1-2: the entries of G'1 sorted by (i, j): pi < pj are seed indices,
+ * packed = (d'1 << 32) | edge id.  cap is the capacity of the host arrays;
+ * *npairs receives the count (ENOMEM if cap is too small, with *npairs set). */
+int steiner_boundary(steiner_graph *g, const uint32_t *seeds, uint32_t k, const steiner_options *opt,
+                     uint64_t *npairs, uint32_t *pi, uint32_t *pj, uint64_t *packed, uint64_t cap);
+
+/* Serving: a request loop over a resident graph.  Requests are admitted while
+ * their per-query device memory fits mem_budget_bytes and a slot is free, are
+ * spliced into the running multi-query pass between relaxation rounds, and
+ * their tails run as soon as their own cells converge. */
+int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes, uint32_t max_slots,
+                          const steiner_options *opt, steiner_server **out);
+int steiner_server_submit(steiner_server *s, const uint32_t *seeds, uint32_t k, uint64_t *ticket);
+/* timeout_us < 0 waits forever.  ETIMEDOUT leaves the request pending. */
+int steiner_server_wait(steiner_server *s, uint64_t ticket, int64_t timeout_us, steiner_result **out);
+/* Bytes a request with k seeds needs on the device (the admission charge). */
+uint64_t steiner_server_query_bytes(const steiner_server *s, uint32_t k);
+int steiner_server_destroy(steiner_server *s);
+
+const char *steiner_strerror(int code);
+const char *steiner_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STEINER_H */

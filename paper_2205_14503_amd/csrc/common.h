@@ -1,0 +1,102 @@
+// Internal types shared by the gfx950 kernels (kernels.hip) and the host
+// engine (engine.cpp).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stn {
+
+constexpr uint64_t KEY_INF = ~0ull;          // unreached vertex key
+constexpr uint32_t DIST_INF = 0xFFFFFFFFu;   // unreached distance (also the saturation limit)
+constexpr uint32_t NONE = 0xFFFFFFFFu;       // no vertex / no predecessor
+constexpr uint32_t MAX_SLOTS = 4096;         // queries resident in one pass (12-bit slot field)
+
+// Near-frontier item encodings.
+//  S item: (slot << 32) | v                    -- a row of degree <= small_max
+//  B item: (slot << 52) | (chunk << 32) | v    -- `chunk`-th piece of a larger row
+__host__ __device__ inline uint64_t s_item(uint32_t slot, uint32_t v) { return ((uint64_t)slot << 32) | v; }
+__host__ __device__ inline uint64_t b_item(uint32_t slot, uint32_t chunk, uint32_t v) {
+    return ((uint64_t)slot << 52) | ((uint64_t)chunk << 32) | v;
+}
+
+// Per-query control, stored structure-of-arrays so the persistent kernel can
+// mirror it in LDS.  thr is the exclusive upper end of the query's current
+// distance bucket: a relaxed vertex with dist < thr is processed in the next
+// round, otherwise it is parked (dirty) until its bucket comes up.
+struct SlotArrays {
+    uint64_t *thr;       // current bucket end
+    uint64_t *thr_prev;  // bucket end before the latest advance
+    uint32_t *carry;     // lower bound on dist of parked vertices (DIST_INF = none)
+    uint32_t *active;    // 1 while resident and unconverged
+    uint32_t *adv;       // 1 if the query advances its bucket this round
+    uint32_t *done;      // 1 once its cells have converged
+    uint32_t *advances;  // bucket advances so far
+};
+
+// Pass-wide control block (one per multi-query pass).
+struct PassCtl {
+    uint32_t round;     // current round r
+    uint32_t all_done;  // 1 when no resident query has work left
+    uint32_t any_adv;   // 1 if some query advances this round
+    uint32_t nslots;    // slots in use (upper bound of active slot ids)
+    uint32_t err;       // device-side error bits
+    uint32_t pad[3];
+};
+
+// Rotating counters: index (r % 3) holds the S and B item counts of the list
+// that round r processes; (r + 1) % 3 is filled during round r; (r + 2) % 3 is
+// cleared during round r.
+struct Counters {
+    uint32_t s[3];
+    uint32_t b[3];
+    uint32_t bar_count;  // persistent-kernel grid barrier
+    uint32_t bar_gen;
+    uint32_t abort;      // set when a barrier wait gives up
+    uint32_t pad[7];
+};
+
+struct DevGraph {
+    uint32_t n;
+    uint32_t nnz;
+    const uint32_t *rp;   // row offsets, n+1 (32-bit: nnz < 2^32)
+    const uint2 *adj;     // (col, w) per CSR entry
+    // Rows of degree > scan_heavy are split into chunks of scan_chunk edges
+    // for the boundary scan; heavy_rows lists them (ascending) and
+    // heavy_chunk_off[h] is the index of row h's first chunk (nheavy+1 entries).
+    // Every other row is scanned by the wave owning its group of 64 rows.
+    uint32_t nheavy;
+    uint32_t nheavy_chunks;
+    const uint32_t *heavy_rows;
+    const uint32_t *heavy_chunk_off;
+    uint32_t scan_heavy;
+    uint32_t scan_chunk;
+};
+
+struct VorParams {
+    DevGraph g;
+    uint64_t *key;       // [slots * n]
+    uint32_t *aux;       // [slots * n]: near-push stamp during the pass, pred after the scan
+    uint8_t *dirty;      // [slots * n]: parked (far) marks
+    uint64_t *items_s[2];
+    uint64_t *items_b[2];
+    uint32_t cap_s, cap_b;
+    Counters *cnt;
+    uint32_t *far_min;   // [3][slots]: min dist parked in round r (rotating)
+    uint32_t *near_mark; // [3][slots]: 1 if the query pushed near items in round r (rotating)
+    SlotArrays slot;     // [slots] each
+    PassCtl *pass;
+    uint32_t nslots;     // allocated slots
+    uint32_t delta;
+    uint32_t small_max;
+    uint32_t chunk;
+};
+
+enum : uint32_t {
+    ERR_DIST_OVERFLOW = 1u,   // some reached vertex has an unreached neighbour after convergence
+    ERR_SUM_OVERFLOW = 2u,    // some cross-cell sum >= 2^32
+    ERR_LIST_OVERFLOW = 4u,   // frontier capacity exceeded (internal bug guard)
+    ERR_ROUND_LIMIT = 8u,     // round safety cap reached
+    ERR_BARRIER_TIMEOUT = 16u // persistent kernel barrier spin cap reached
+};
+
+}  // namespace stn

@@ -1,0 +1,555 @@
+// Host engine and C ABI of the MI355X Steiner tree library (include/steiner.h).
+//
+// A graph lives on one device as a 32-bit row-offset array plus interleaved
+// (col, w) pairs.  A solve runs a multi-query pass (a single query is a pass
+// with one slot): slot start -> relaxation rounds to convergence -> fused
+// pred/boundary scan -> G'1 compaction -> MST of G'1 on the host (Prim under
+// the strict order (d'1, i, j); Alg. 2 Step 3 keeps this step sequential) ->
+// predecessor-walk expansion on the device -> sorted edge list and D.
+#include "engine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <queue>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+namespace stn {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+// Allocation fault injection for error-path tests: STEINER_FAULT_ALLOC_AFTER=N
+// makes the (N+1)-th device allocation of the process fail.
+static long g_alloc_calls = 0;
+static long fault_alloc_after() {
+    static long v = -2;
+    if (v == -2) {
+        const char *s = getenv("STEINER_FAULT_ALLOC_AFTER");
+        v = s ? atol(s) : -1;
+    }
+    return v;
+}
+
+int dev_alloc(void **p, size_t bytes) {
+    long lim = fault_alloc_after();
+    long c = __atomic_fetch_add(&g_alloc_calls, 1, __ATOMIC_RELAXED);
+    if (lim >= 0 && c >= lim) return fail(STEINER_ENOMEM, "injected allocation failure (%zu bytes)", bytes);
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(STEINER_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return STEINER_OK;
+}
+
+void dev_free(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+int hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return STEINER_OK;
+    (void)hipGetLastError();
+    return fail(STEINER_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------- buffers
+
+void DevBuf::release() {
+    dev_free(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+int DevBuf::ensure(size_t want) {
+    if (want <= bytes && ptr) return STEINER_OK;
+    release();
+    size_t cap = want + want / 8 + 256;
+    int rc = dev_alloc(&ptr, cap);
+    if (rc) return rc;
+    bytes = cap;
+    return STEINER_OK;
+}
+
+void HostPinned::release() {
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+int HostPinned::ensure(size_t want) {
+    if (want <= bytes && ptr) return STEINER_OK;
+    release();
+    size_t cap = want + want / 8 + 256;
+    if (hipHostMalloc(&ptr, cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+        return fail(STEINER_ENOMEM, "hipHostMalloc(%zu) failed", cap);
+    }
+    bytes = cap;
+    return STEINER_OK;
+}
+
+// ------------------------------------------------------------- options
+
+Options resolve_options(const steiner_graph *g, const steiner_options *o) {
+    Options r;
+    r.delta = g->default_delta;
+    r.driver = 1;
+    r.block = 256;
+    r.grid = 0;
+    r.small_max = 64;
+    r.chunk = 512;
+    r.timing = false;
+    if (const char *s = getenv("STEINER_DRIVER")) r.driver = (uint32_t)atoi(s);
+    if (const char *s = getenv("STEINER_DELTA")) r.delta = (uint32_t)strtoul(s, nullptr, 10);
+    if (o) {
+        if (o->delta) r.delta = o->delta;
+        if (o->driver) r.driver = o->driver;
+        if (o->block) r.block = o->block;
+        if (o->grid) r.grid = o->grid;
+        if (o->small_max) r.small_max = o->small_max;
+        if (o->chunk) r.chunk = o->chunk;
+        r.timing = (o->flags & STEINER_FLAG_TIMING) != 0;
+    }
+    if (r.delta == 0) r.delta = 1;
+    if (r.block < 64 || r.block > 1024 || r.block % 64) r.block = 256;
+    if (r.chunk < 64) r.chunk = 64;
+    if (r.grid == 0) r.grid = (uint32_t)std::max(1, g->cu_count) * (r.driver == 2 ? 2u : 4u) * (1024u / r.block);
+    return r;
+}
+
+// ------------------------------------------------------------- pair index
+
+// (i, j), i < j, of lower-triangular index p = j(j-1)/2 + i.
+void pair_from_index(uint64_t p, uint32_t *i, uint32_t *j) {
+    uint64_t jj = (uint64_t)((1.0 + std::sqrt(1.0 + 8.0 * (double)p)) / 2.0);
+    while (jj * (jj - 1) / 2 > p) jj--;
+    while ((jj + 1) * jj / 2 <= p) jj++;
+    *j = (uint32_t)jj;
+    *i = (uint32_t)(p - jj * (jj - 1) / 2);
+}
+
+// MST of G'1 by Prim's algorithm under the strict order (d'1, i, j); the
+// order is total, so the tree is the unique one any correct MST code returns.
+// Returns the chosen list positions, or EDISCONNECTED.
+int prim_mst(uint32_t k, const std::vector<uint32_t> &pidx, const std::vector<uint64_t> &pval,
+             std::vector<uint32_t> &chosen) {
+    const size_t m = pidx.size();
+    std::vector<uint32_t> pi(m), pj(m);
+    std::vector<uint32_t> deg(k + 1, 0);
+    for (size_t t = 0; t < m; t++) {
+        pair_from_index(pidx[t], &pi[t], &pj[t]);
+        deg[pi[t] + 1]++;
+        deg[pj[t] + 1]++;
+    }
+    for (uint32_t v = 0; v < k; v++) deg[v + 1] += deg[v];
+    std::vector<uint32_t> adj(2 * m), fill(deg.begin(), deg.end() - 1);
+    for (size_t t = 0; t < m; t++) {
+        adj[fill[pi[t]]++] = (uint32_t)t;
+        adj[fill[pj[t]]++] = (uint32_t)t;
+    }
+    typedef std::tuple<uint32_t, uint32_t, uint32_t, uint32_t> HE;  // (d'1, i, j, list position)
+    std::priority_queue<HE, std::vector<HE>, std::greater<HE>> pq;
+    std::vector<uint8_t> in(k, 0);
+    chosen.clear();
+    auto add = [&](uint32_t v) {
+        in[v] = 1;
+        for (uint32_t a = deg[v]; a < deg[v + 1]; a++) {
+            uint32_t t = adj[a];
+            uint32_t o = pi[t] == v ? pj[t] : pi[t];
+            if (!in[o]) pq.emplace((uint32_t)(pval[t] >> 32), pi[t], pj[t], t);
+        }
+    };
+    add(0);
+    while (!pq.empty() && chosen.size() + 1 < k) {
+        HE top = pq.top();
+        pq.pop();
+        uint32_t t = std::get<3>(top);
+        uint32_t o = in[pi[t]] ? pj[t] : pi[t];
+        if (in[pi[t]] && in[pj[t]]) continue;
+        chosen.push_back(t);
+        add(o);
+    }
+    return chosen.size() + 1 == k ? STEINER_OK : STEINER_EDISCONNECTED;
+}
+
+}  // namespace stn
+
+using namespace stn;
+
+// ===================================================================== graph
+
+static __global__ void k_validate_rows(const uint64_t *rp, uint32_t n, uint64_t nnz, uint8_t *is_start,
+                                       uint32_t *bad) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        uint64_t a = rp[v], b = rp[v + 1];
+        if (b < a || b > nnz) atomicOr(bad, 1u);
+        else if (a < b) is_start[a] = 1;
+    }
+}
+
+static __global__ void k_validate_entries(const uint32_t *col, const uint32_t *w, uint64_t nnz, uint32_t n,
+                                          const uint8_t *is_start, uint32_t *bad) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t c = col[e];
+        if (c >= n || w[e] == 0) atomicOr(bad, 2u);
+        if (e + 1 < nnz && !is_start[e + 1] && col[e + 1] < c) atomicOr(bad, 4u);
+    }
+}
+
+static __global__ void k_convert(const uint64_t *rp64, uint32_t n, const uint32_t *col, const uint32_t *w,
+                                 uint64_t nnz, uint32_t *rp32, uint2 *adj) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += stride) rp32[v] = (uint32_t)rp64[v];
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) adj[e] = make_uint2(col[e], w[e]);
+}
+
+static __global__ void k_weight_sum(const uint32_t *w, uint64_t nnz, unsigned long long *sum) {
+    unsigned long long s = 0;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (uint64_t)gridDim.x * blockDim.x) s += w[e];
+    atomicAdd(sum, s);
+}
+
+// Symmetry: every entry (a, b, w) has a partner (b, a, w); checked by binary
+// search for (a, w) in row b among equal columns.
+static __global__ void k_validate_symmetry(const uint64_t *rp, const uint32_t *col, const uint32_t *w, uint32_t n,
+                                           uint32_t *bad) {
+    for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
+        for (uint64_t e = rp[a]; e < rp[a + 1]; e++) {
+            uint32_t b = col[e], wt = w[e];
+            uint64_t lo = rp[b], hi = rp[b + 1];
+            while (lo < hi) {
+                uint64_t mid = (lo + hi) / 2;
+                if (col[mid] < a) lo = mid + 1; else hi = mid;
+            }
+            bool ok = false;
+            for (uint64_t f = lo; f < rp[b + 1] && col[f] == a; f++)
+                if (w[f] == wt) { ok = true; break; }
+            if (!ok) { atomicOr(bad, 8u); return; }
+        }
+    }
+}
+
+static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t *d_col, const uint32_t *d_w,
+                        uint32_t flags) {
+    const uint32_t n = g->n;
+    const uint64_t nnz = g->nnz;
+    hipStream_t s = g->stream;
+    int rc;
+    uint64_t ends[2];
+    if ((rc = hip_check(hipMemcpyAsync(&ends[0], d_rp64, 8, hipMemcpyDeviceToHost, s), "row_ptr[0]"))) return rc;
+    if ((rc = hip_check(hipMemcpyAsync(&ends[1], d_rp64 + n, 8, hipMemcpyDeviceToHost, s), "row_ptr[n]"))) return rc;
+    if ((rc = hip_check(hipStreamSynchronize(s), "sync"))) return rc;
+    if (ends[0] != 0 || ends[1] != nnz) return fail(STEINER_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] must be nnz");
+    void *is_start = nullptr, *bad = nullptr;
+    if ((rc = dev_alloc(&is_start, nnz + 1))) return rc;
+    if ((rc = dev_alloc(&bad, 16))) { dev_free(is_start); return rc; }
+    (void)hipMemsetAsync(is_start, 0, nnz + 1, s);
+    (void)hipMemsetAsync(bad, 0, 16, s);
+    hipLaunchKernelGGL(k_validate_rows, dim3(2048), dim3(256), 0, s, d_rp64, n, nnz, (uint8_t *)is_start, (uint32_t *)bad);
+    hipLaunchKernelGGL(k_validate_entries, dim3(4096), dim3(256), 0, s, d_col, d_w, nnz, n, (const uint8_t *)is_start,
+                       (uint32_t *)bad);
+    uint32_t hbad = 0;
+    rc = hip_check(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s), "validate");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "validate sync");
+    if (!rc && !hbad && (flags & 1u)) {
+        hipLaunchKernelGGL(k_validate_symmetry, dim3(2048), dim3(256), 0, s, d_rp64, d_col, d_w, n, (uint32_t *)bad);
+        rc = hip_check(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s), "symmetry");
+        if (!rc) rc = hip_check(hipStreamSynchronize(s), "symmetry sync");
+    }
+    dev_free(is_start);
+    if (rc) { dev_free(bad); return rc; }
+    if (hbad) {
+        dev_free(bad);
+        return fail(STEINER_EINVAL, "invalid graph:%s%s%s%s", (hbad & 1) ? " non-monotone row_ptr" : "",
+                    (hbad & 2) ? " column out of range or zero weight" : "", (hbad & 4) ? " unsorted row" : "",
+                    (hbad & 8) ? " asymmetric" : "");
+    }
+    if ((rc = dev_alloc((void **)&g->d_rp, ((size_t)n + 1) * 4))) { dev_free(bad); return rc; }
+    if ((rc = dev_alloc((void **)&g->d_adj, nnz * 8))) { dev_free(bad); return rc; }
+    hipLaunchKernelGGL(k_convert, dim3(4096), dim3(256), 0, s, d_rp64, n, d_col, d_w, nnz, g->d_rp, g->d_adj);
+    (void)hipMemsetAsync(bad, 0, 16, s);
+    hipLaunchKernelGGL(k_weight_sum, dim3(1024), dim3(256), 0, s, d_w, nnz, (unsigned long long *)bad);
+    unsigned long long wsum = 0;
+    g->h_rp.resize((size_t)n + 1);
+    rc = hip_check(hipMemcpyAsync(&wsum, bad, 8, hipMemcpyDeviceToHost, s), "weights");
+    if (!rc) rc = hip_check(hipMemcpyAsync(g->h_rp.data(), d_rp64, ((size_t)n + 1) * 8, hipMemcpyDeviceToHost, s), "row_ptr");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "convert");
+    dev_free(bad);
+    if (rc) return rc;
+    // Heavy rows of the boundary scan and the default bucket width.
+    const uint32_t scan_heavy = 1024, scan_chunk = 1024;
+    std::vector<uint32_t> hrows, hoff;
+    hoff.push_back(0);
+    for (uint32_t v = 0; v < n; v++) {
+        uint64_t d = g->h_rp[v + 1] - g->h_rp[v];
+        if (d > scan_heavy) {
+            hrows.push_back(v);
+            hoff.push_back(hoff.back() + (uint32_t)((d + scan_chunk - 1) / scan_chunk));
+        }
+    }
+    g->nheavy = (uint32_t)hrows.size();
+    if ((rc = dev_alloc((void **)&g->d_heavy_rows, hrows.size() * 4 + 4))) return rc;
+    if ((rc = dev_alloc((void **)&g->d_heavy_off, hoff.size() * 4))) return rc;
+    if (!hrows.empty())
+        (void)hipMemcpyAsync(g->d_heavy_rows, hrows.data(), hrows.size() * 4, hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(g->d_heavy_off, hoff.data(), hoff.size() * 4, hipMemcpyHostToDevice, s);
+    if ((rc = hip_check(hipStreamSynchronize(s), "heavy rows"))) return rc;
+    DevGraph &dg = g->dg;
+    dg.n = n;
+    dg.nnz = (uint32_t)nnz;
+    dg.rp = g->d_rp;
+    dg.adj = g->d_adj;
+    dg.nheavy = g->nheavy;
+    dg.nheavy_chunks = hoff.back();
+    dg.heavy_rows = g->d_heavy_rows;
+    dg.heavy_chunk_off = g->d_heavy_off;
+    dg.scan_heavy = scan_heavy;
+    dg.scan_chunk = scan_chunk;
+    const double avg_w = nnz ? (double)wsum / (double)nnz : 1.0;
+    const double avg_deg = n ? (double)nnz / (double)n : 1.0;
+    double d = 2.0 * avg_w / std::max(1.0, avg_deg);
+    g->default_delta = (uint32_t)std::max(1.0, std::min(d, 4.0e9));
+    return STEINER_OK;
+}
+
+static int graph_create(uint32_t n, uint64_t nnz, int device, void *stream, steiner_graph **out) {
+    if (!out) return fail(STEINER_EINVAL, "out is NULL");
+    if (n == 0) return fail(STEINER_EINVAL, "n must be > 0");
+    if (n == 0xFFFFFFFFu) return fail(STEINER_EINVAL, "n must be < 2^32-1");
+    if (nnz >= (1ull << 32)) return fail(STEINER_EINVAL, "nnz must be < 2^32 (edge ids are 32-bit)");
+    int rc = hip_check(hipSetDevice(device), "hipSetDevice");
+    if (rc) return rc;
+    steiner_graph *g = new steiner_graph();
+    g->device = device;
+    g->stream = (hipStream_t)stream;
+    g->n = n;
+    g->nnz = nnz;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) g->cu_count = prop.multiProcessorCount;
+    *out = g;
+    return STEINER_OK;
+}
+
+extern "C" int steiner_graph_upload(uint32_t n, uint64_t nnz, const uint64_t *row_ptr, const uint32_t *col,
+                                    const uint32_t *w, int device, void *hip_stream, uint32_t flags,
+                                    steiner_graph **out) {
+    if (!row_ptr || (nnz && (!col || !w))) return fail(STEINER_EINVAL, "NULL array");
+    steiner_graph *g = nullptr;
+    int rc = graph_create(n, nnz, device, hip_stream, &g);
+    if (rc) return rc;
+    void *rp = nullptr, *c = nullptr, *ww = nullptr;
+    rc = dev_alloc(&rp, ((size_t)n + 1) * 8);
+    if (!rc) rc = dev_alloc(&c, nnz * 4);
+    if (!rc) rc = dev_alloc(&ww, nnz * 4);
+    if (!rc) rc = hip_check(hipMemcpyAsync(rp, row_ptr, ((size_t)n + 1) * 8, hipMemcpyHostToDevice, g->stream), "H2D row_ptr");
+    if (!rc && nnz) rc = hip_check(hipMemcpyAsync(c, col, nnz * 4, hipMemcpyHostToDevice, g->stream), "H2D col");
+    if (!rc && nnz) rc = hip_check(hipMemcpyAsync(ww, w, nnz * 4, hipMemcpyHostToDevice, g->stream), "H2D w");
+    if (!rc) rc = finish_graph(g, (const uint64_t *)rp, (const uint32_t *)c, (const uint32_t *)ww, flags);
+    (void)hipStreamSynchronize(g->stream);
+    dev_free(rp);
+    dev_free(c);
+    dev_free(ww);
+    if (rc) {
+        std::string keep = g_last_error;
+        steiner_graph_free(g);
+        g_last_error = keep;
+        return rc;
+    }
+    *out = g;
+    return STEINER_OK;
+}
+
+extern "C" int steiner_graph_upload_device(uint32_t n, uint64_t nnz, const void *d_row_ptr, const void *d_col,
+                                           const void *d_w, int device, void *hip_stream, uint32_t flags,
+                                           steiner_graph **out) {
+    if (!d_row_ptr || (nnz && (!d_col || !d_w))) return fail(STEINER_EINVAL, "NULL array");
+    steiner_graph *g = nullptr;
+    int rc = graph_create(n, nnz, device, hip_stream, &g);
+    if (rc) return rc;
+    rc = finish_graph(g, (const uint64_t *)d_row_ptr, (const uint32_t *)d_col, (const uint32_t *)d_w, flags);
+    if (rc) {
+        std::string keep = g_last_error;
+        steiner_graph_free(g);
+        g_last_error = keep;
+        return rc;
+    }
+    *out = g;
+    return STEINER_OK;
+}
+
+extern "C" int steiner_graph_free(steiner_graph *g) {
+    if (!g) return STEINER_OK;
+    (void)hipSetDevice(g->device);
+    (void)hipStreamSynchronize(g->stream);
+    g->ws.release();
+    dev_free(g->d_rp);
+    dev_free(g->d_adj);
+    dev_free(g->d_heavy_rows);
+    dev_free(g->d_heavy_off);
+    delete g;
+    return STEINER_OK;
+}
+
+// ==================================================================== results
+
+extern "C" int steiner_result_edges(const steiner_result *r, uint64_t *m, const uint32_t **a, const uint32_t **b,
+                                    const uint32_t **w) {
+    if (!r || !m) return fail(STEINER_EINVAL, "NULL argument");
+    *m = r->a.size();
+    if (a) *a = r->a.data();
+    if (b) *b = r->b.data();
+    if (w) *w = r->w.data();
+    return STEINER_OK;
+}
+
+extern "C" uint64_t steiner_result_total(const steiner_result *r) { return r ? r->total : 0; }
+
+extern "C" int steiner_result_stats(const steiner_result *r, steiner_stats *out) {
+    if (!r || !out) return fail(STEINER_EINVAL, "NULL argument");
+    *out = r->stats;
+    return STEINER_OK;
+}
+
+extern "C" void steiner_result_free(steiner_result *r) { delete r; }
+
+extern "C" const char *steiner_strerror(int code) {
+    switch (code) {
+    case STEINER_OK: return "ok";
+    case STEINER_EINVAL: return "invalid argument";
+    case STEINER_ENOMEM: return "out of memory";
+    case STEINER_EDISCONNECTED: return "seeds are not connected";
+    case STEINER_EOVERFLOW: return "distance overflow";
+    case STEINER_EDEVICE: return "device error";
+    case STEINER_ETIMEDOUT: return "timed out";
+    case STEINER_ECANCELED: return "canceled";
+    default: return "unknown error";
+    }
+}
+
+extern "C" const char *steiner_last_error(void) { return g_last_error.c_str(); }
+
+// ===================================================================== solves
+
+// Sorted, distinct seeds; EINVAL for k == 0 or a seed >= n.
+int stn::canon_seeds(const steiner_graph *g, const uint32_t *seeds, uint32_t k, std::vector<uint32_t> &S) {
+    if (k == 0) return fail(STEINER_EINVAL, "k must be > 0");
+    if (!seeds) return fail(STEINER_EINVAL, "seeds is NULL");
+    S.assign(seeds, seeds + k);
+    for (uint32_t s : S)
+        if (s >= g->n) return fail(STEINER_EINVAL, "seed %u >= n", s);
+    std::sort(S.begin(), S.end());
+    S.erase(std::unique(S.begin(), S.end()), S.end());
+    return STEINER_OK;
+}
+
+extern "C" int steiner_solve(steiner_graph *g, const uint32_t *seeds, uint32_t k, const steiner_options *opt,
+                             steiner_result **out) {
+    if (!g || !out) return fail(STEINER_EINVAL, "NULL argument");
+    const uint32_t *ps[1] = {seeds};
+    uint32_t ks[1] = {k};
+    steiner_result *res[1] = {nullptr};
+    int st[1] = {0};
+    int rc = steiner_solve_batch(g, 1, ps, ks, opt, res, st);
+    if (rc) return rc;
+    if (st[0]) return st[0];
+    *out = res[0];
+    return STEINER_OK;
+}
+
+extern "C" int steiner_solve_batch(steiner_graph *g, uint32_t q, const uint32_t *const *seeds, const uint32_t *ks,
+                                   const steiner_options *opt, steiner_result **outs, int *status) {
+    if (!g || !outs || !status || (q && (!seeds || !ks))) return fail(STEINER_EINVAL, "NULL argument");
+    if (q == 0) return STEINER_OK;
+    if (q > MAX_SLOTS) return fail(STEINER_EINVAL, "at most %u queries per batch", MAX_SLOTS);
+    std::lock_guard<std::mutex> lk(g->mu);
+    int rc = hip_check(hipSetDevice(g->device), "hipSetDevice");
+    if (rc) return rc;
+    Options o = resolve_options(g, opt);
+    std::vector<Query> qs(q);
+    for (uint32_t i = 0; i < q; i++) {
+        outs[i] = nullptr;
+        status[i] = canon_seeds(g, seeds[i], ks[i], qs[i].S);
+        qs[i].status = status[i];
+    }
+    rc = run_pass(g, o, qs);
+    if (rc) return rc;
+    for (uint32_t i = 0; i < q; i++) {
+        status[i] = qs[i].status;
+        if (qs[i].status == STEINER_OK) outs[i] = qs[i].result.release();
+    }
+    return STEINER_OK;
+}
+
+extern "C" int steiner_voronoi(steiner_graph *g, const uint32_t *seeds, uint32_t k, const steiner_options *opt,
+                               uint64_t *key_out, uint32_t *pred_out) {
+    if (!g || !key_out || !pred_out) return fail(STEINER_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(g->mu);
+    int rc = hip_check(hipSetDevice(g->device), "hipSetDevice");
+    if (rc) return rc;
+    std::vector<Query> qs(1);
+    if ((rc = canon_seeds(g, seeds, k, qs[0].S))) return rc;
+    if (qs[0].S.size() < 2) return fail(STEINER_EINVAL, "steiner_voronoi needs at least 2 distinct seeds");
+    qs[0].want_key = key_out;
+    qs[0].want_pred = pred_out;
+    qs[0].stop_after = STOP_AFTER_SCAN;
+    Options o = resolve_options(g, opt);
+    rc = run_pass(g, o, qs);
+    if (rc) return rc;
+    return qs[0].status;
+}
+
+extern "C" int steiner_boundary(steiner_graph *g, const uint32_t *seeds, uint32_t k, const steiner_options *opt,
+                                uint64_t *npairs, uint32_t *pi, uint32_t *pj, uint64_t *packed, uint64_t cap) {
+    if (!g || !npairs || (cap && (!pi || !pj || !packed))) return fail(STEINER_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(g->mu);
+    int rc = hip_check(hipSetDevice(g->device), "hipSetDevice");
+    if (rc) return rc;
+    std::vector<Query> qs(1);
+    if ((rc = canon_seeds(g, seeds, k, qs[0].S))) return rc;
+    if (qs[0].S.size() < 2) return fail(STEINER_EINVAL, "steiner_boundary needs at least 2 distinct seeds");
+    qs[0].stop_after = STOP_AFTER_COMPACT;
+    Options o = resolve_options(g, opt);
+    rc = run_pass(g, o, qs);
+    if (rc) return rc;
+    if (qs[0].status) return qs[0].status;
+    const size_t m = qs[0].pidx.size();
+    std::vector<size_t> ord(m);
+    for (size_t t = 0; t < m; t++) ord[t] = t;
+    std::sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return qs[0].pidx[x] < qs[0].pidx[y]; });
+    *npairs = m;
+    if (m > cap) return fail(STEINER_ENOMEM, "G'1 has %zu entries, capacity %llu", m, (unsigned long long)cap);
+    // lower-triangular index order is (j, i) order; report sorted by (i, j)
+    std::vector<std::tuple<uint32_t, uint32_t, uint64_t>> rows(m);
+    for (size_t t = 0; t < m; t++) {
+        uint32_t i, j;
+        pair_from_index(qs[0].pidx[ord[t]], &i, &j);
+        rows[t] = std::make_tuple(i, j, qs[0].pval[ord[t]]);
+    }
+    std::sort(rows.begin(), rows.end());
+    for (size_t t = 0; t < m; t++) {
+        pi[t] = std::get<0>(rows[t]);
+        pj[t] = std::get<1>(rows[t]);
+        packed[t] = std::get<2>(rows[t]);
+    }
+    return STEINER_OK;
+}

@@ -1,0 +1,882 @@
+// gfx950 (MI355X) kernels of the Voronoi-cell Steiner tree hot path
+// (arXiv:2205.14503, Alg. 2 Steps 1, 2, 4-6).
+//
+// Step 1, the Voronoi cells (Alg. 4's relaxation), runs as rounds of a
+// distance-bucketed label-correcting pass over a frontier of improved
+// vertices.  A vertex key packs (dist << 32) | seed index, so one 64-bit
+// atomicMin applies the lexicographic (distance, seed index) order; the pass
+// converges to the unique fixed point key[v] = min_i (d(s_i, v), i) whatever
+// the processing order.  Improved vertices whose distance is inside the
+// query's current bucket go to the next round's frontier; the others are
+// parked with a dirty byte until their bucket comes up (Section IV's message
+// prioritisation, realised as distance buckets instead of a priority queue).
+//
+// Frontier rows of degree <= small_max are expanded wave-cooperatively: a
+// wave takes 64 items, prefix-sums their degrees and walks the combined edge
+// range 64 edges per step (coalesced 8-byte (col, w) loads).  Larger rows are
+// pushed as fixed chunks that any wave can take, so hubs spread over the GPU.
+//
+// Step 2 (Alg. 5) and the canonical predecessor share one streaming pass over
+// the CSR: every entry gathers its neighbour's key once.
+#include "kernels.h"
+
+namespace stn {
+
+#define DEVI __device__ __forceinline__
+
+constexpr uint32_t MAX_WAVES = 16;  // 1024-thread workgroups
+constexpr uint32_t PERSIST_SLOTS = 256;
+
+DEVI uint32_t lane() { return __lane_id(); }
+
+DEVI uint64_t ld_agent(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEVI uint32_t ld_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Orders LDS traffic between the lanes of one wave.
+DEVI void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+DEVI uint32_t wave_incl_scan(uint32_t x) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, 64);
+        if (lane() >= (uint32_t)d) x += y;
+    }
+    return x;
+}
+
+DEVI uint32_t wave_min(uint32_t x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x = min(x, (uint32_t)__shfl_xor(x, d, 64));
+    return x;
+}
+
+DEVI uint32_t lanes_below(uint64_t mask) { return (uint32_t)__popcll(mask & ((1ull << lane()) - 1ull)); }
+
+struct RoundIdx {
+    uint32_t r;      // round number
+    uint32_t cur;    // list read this round
+    uint32_t nxt;    // list filled this round
+    uint32_t c_nxt;  // counter set filled this round
+    uint32_t b;      // near_mark / far_min buffer written this round
+};
+
+DEVI RoundIdx round_idx(uint32_t r) { return RoundIdx{r, r & 1u, (r + 1) & 1u, (r + 1) % 3u, r % 3u}; }
+
+// Wave-aggregated append of S items (one atomic per wave).
+DEVI void append_s(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, uint64_t item) {
+    uint64_t m = __ballot(pred);
+    if (m == 0) return;
+    uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane() == leader) base = atomicAdd(&P.cnt->s[cidx], (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    if (pred) {
+        uint32_t pos = base + lanes_below(m);
+        if (pos < P.cap_s)
+            P.items_s[list][pos] = item;
+        else
+            atomicOr(&P.pass->err, ERR_LIST_OVERFLOW);
+    }
+}
+
+// Wave-aggregated append of the chunks of rows larger than small_max.
+DEVI void append_b(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, uint32_t slot, uint32_t v,
+                   uint32_t deg) {
+    uint64_t m = __ballot(pred);
+    if (m == 0) return;
+    uint32_t nch = pred ? (deg + P.chunk - 1) / P.chunk : 0;
+    uint32_t incl = wave_incl_scan(nch);
+    uint32_t total = __shfl(incl, 63, 64);
+    uint32_t base = 0;
+    if (lane() == 0) base = atomicAdd(&P.cnt->b[cidx], total);
+    base = __shfl(base, 0, 64);
+    if (pred) {
+        uint32_t pos = base + incl - nch;
+        for (uint32_t c = 0; c < nch; c++) {
+            if (pos + c < P.cap_b) {
+                P.items_b[list][pos + c] = b_item(slot, c, v);
+            } else {
+                atomicOr(&P.pass->err, ERR_LIST_OVERFLOW);
+                break;
+            }
+        }
+    }
+}
+
+// Relax one edge (src key ksrc, target u, weight w) of query `slot` and
+// schedule u if its key improved.  Must be reached by every lane of the wave.
+DEVI void relax_push(const VorParams &P, const RoundIdx &R, const uint64_t *thr, bool valid, uint32_t slot,
+                     uint64_t ksrc, uint32_t u, uint32_t w) {
+    const uint32_t n = P.g.n;
+    bool improved = false;
+    uint32_t nd = 0;
+    if (valid) {
+        uint64_t d = (ksrc >> 32) + (uint64_t)w;
+        if (d < DIST_INF) {  // a distance of 2^32-1 or more is never stored
+            uint64_t cand = (d << 32) | (ksrc & 0xFFFFFFFFull);
+            uint64_t *kp = P.key + (size_t)slot * n + u;
+            if (cand < *kp) {  // possibly stale (larger) value: filter only
+                uint64_t old = atomicMin((unsigned long long *)kp, (unsigned long long)cand);
+                if (cand < old) {
+                    improved = true;
+                    nd = (uint32_t)d;
+                }
+            }
+        }
+    }
+    bool claim = false, park = false;
+    uint32_t deg = 0;
+    if (improved) {
+        if ((uint64_t)nd < thr[slot]) {
+            uint32_t *sp = P.aux + (size_t)slot * n + u;
+            if (atomicExch(sp, R.r + 1) != R.r + 1) {
+                claim = true;
+                deg = P.g.rp[u + 1] - P.g.rp[u];
+                uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + slot;
+                if (*nm == 0) *nm = 1;
+            }
+        } else {
+            park = true;
+        }
+    }
+    if (park) {
+        P.dirty[(size_t)slot * n + u] = 1;
+        uint32_t *fm = P.far_min + (size_t)R.b * P.nslots + slot;
+        if (nd < *fm) atomicMin(fm, nd);
+    }
+    append_s(P, R.nxt, R.c_nxt, claim && deg <= P.small_max, s_item(slot, u));
+    append_b(P, R.nxt, R.c_nxt, claim && deg > P.small_max, slot, u, deg);
+}
+
+struct WaveScratch {
+    uint32_t incl[64];
+    uint32_t beg[64];
+    uint32_t aux[64];
+    uint32_t flag[64];
+    uint64_t key[64];
+};
+
+// One wave expands 64 frontier items of small degree.
+DEVI void process_s_group(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t gidx,
+                          uint32_t cnt, WaveScratch *L) {
+    const uint32_t ln = lane();
+    const uint32_t idx = gidx * 64 + ln;
+    uint32_t slot = 0, beg = 0, deg = 0;
+    uint64_t kv = KEY_INF;
+    if (idx < cnt) {
+        uint64_t it = P.items_s[R.cur][idx];
+        slot = (uint32_t)(it >> 32);
+        uint32_t v = (uint32_t)it;
+        kv = ld_agent(P.key + (size_t)slot * P.g.n + v);
+        beg = P.g.rp[v];
+        deg = P.g.rp[v + 1] - beg;
+        if (kv == KEY_INF) deg = 0;
+    }
+    const uint32_t incl = wave_incl_scan(deg);
+    const uint32_t total = __shfl(incl, 63, 64);
+    L->incl[ln] = incl;
+    L->beg[ln] = beg;
+    L->aux[ln] = slot;
+    L->key[ln] = kv;
+    wave_sync();
+    for (uint32_t base = 0; base < total; base += 64) {
+        const uint32_t t = base + ln;
+        const bool valid = t < total;
+        uint32_t j = 0;
+        if (valid) {
+            uint32_t lo = 0, hi = 63;
+            while (lo < hi) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (L->incl[mid] > t) hi = mid; else lo = mid + 1;
+            }
+            j = lo;
+        }
+        const uint32_t ex = j ? L->incl[j - 1] : 0;
+        uint2 a = make_uint2(0, 0);
+        if (valid) a = P.g.adj[L->beg[j] + (t - ex)];
+        relax_push(P, R, thr, valid, L->aux[j], L->key[j], a.x, a.y);
+    }
+    wave_sync();
+}
+
+// One wave expands one chunk of a large row.
+DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t idx) {
+    const uint64_t it = P.items_b[R.cur][idx];
+    const uint32_t slot = (uint32_t)(it >> 52);
+    const uint32_t c = (uint32_t)(it >> 32) & 0xFFFFFu;
+    const uint32_t v = (uint32_t)it;
+    const uint64_t kv = ld_agent(P.key + (size_t)slot * P.g.n + v);
+    const uint32_t beg = P.g.rp[v] + c * P.chunk;
+    const uint32_t lim = P.g.rp[v + 1];
+    uint32_t end = (lim - beg > P.chunk) ? beg + P.chunk : lim;
+    if (kv == KEY_INF) end = beg;
+    for (uint32_t e0 = beg; e0 < end; e0 += 64) {
+        const uint32_t e = e0 + lane();
+        const bool valid = e < end;
+        uint2 a = make_uint2(0, 0);
+        if (valid) a = P.g.adj[e];
+        relax_push(P, R, thr, valid, slot, kv, a.x, a.y);
+    }
+}
+
+DEVI void relax_round_body(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t cs, uint32_t cb,
+                           WaveScratch *L, uint32_t wave_gid, uint32_t nwaves) {
+    const uint32_t ng = (cs + 63) / 64;
+    const uint32_t units = ng + cb;
+    for (uint32_t u = wave_gid; u < units; u += nwaves) {
+        if (u < ng)
+            process_s_group(P, R, thr, u, cs, L);
+        else
+            process_b_chunk(P, R, thr, u - ng);
+    }
+}
+
+// Bucket decision for one query at the end of round r (identical inputs give
+// identical outputs, so the persistent kernel can evaluate it redundantly in
+// every workgroup).
+DEVI void decide_slot(const VorParams &P, uint32_t r, uint32_t q, uint64_t *thr, uint64_t *thr_prev,
+                      uint32_t *carry, uint32_t *active, uint32_t *adv, uint32_t *done, uint32_t *advances,
+                      bool &any_adv, bool &any_active) {
+    adv[q] = 0;
+    if (!active[q]) return;
+    const uint32_t b = r % 3u;
+    uint32_t c = min(carry[q], ld_agent(P.far_min + (size_t)b * P.nslots + q));
+    const bool has_near = ld_agent(P.near_mark + (size_t)b * P.nslots + q) != 0;
+    if (!has_near) {
+        if (c == DIST_INF) {
+            active[q] = 0;
+            done[q] = 1;
+        } else {
+            const uint64_t dl = P.delta;
+            thr_prev[q] = thr[q];
+            thr[q] = ((uint64_t)c / dl + 1) * dl;
+            c = DIST_INF;
+            adv[q] = 1;
+            advances[q] += 1;
+            any_adv = true;
+        }
+    }
+    carry[q] = c;
+    if (active[q]) any_active = true;
+}
+
+// Parked vertices of every advancing query whose distance falls below the new
+// bucket end join the next round's frontier; stale marks are cleared; the
+// minimum parked distance left over feeds the next decision.
+DEVI void advance_body(const VorParams &P, uint32_t r, const uint64_t *thr, const uint64_t *thr_prev,
+                       const uint32_t *adv, uint32_t wave_gid, uint32_t nwaves) {
+    const uint32_t n = P.g.n;
+    const RoundIdx R = round_idx(r);
+    for (uint32_t q = 0; q < P.nslots; q++) {
+        if (!adv[q]) continue;
+        const uint64_t lo = thr_prev[q], hi = thr[q];
+        uint32_t kept = DIST_INF;
+        for (uint32_t base = wave_gid * 64; base < n; base += nwaves * 64) {
+            const uint32_t v = base + lane();
+            bool push = false;
+            uint32_t deg = 0;
+            if (v < n) {
+                const size_t o = (size_t)q * n + v;
+                if (P.dirty[o]) {
+                    const uint32_t d = (uint32_t)(ld_agent(P.key + o) >> 32);
+                    if (d < lo) {
+                        P.dirty[o] = 0;
+                    } else if (d < hi) {
+                        P.dirty[o] = 0;
+                        P.aux[o] = r + 1;
+                        deg = P.g.rp[v + 1] - P.g.rp[v];
+                        push = true;
+                    } else {
+                        kept = min(kept, d);
+                    }
+                }
+            }
+            append_s(P, R.nxt, R.c_nxt, push && deg <= P.small_max, s_item(q, v));
+            append_b(P, R.nxt, R.c_nxt, push && deg > P.small_max, q, v, deg);
+        }
+        kept = wave_min(kept);
+        if (lane() == 0 && kept != DIST_INF) atomicMin(P.far_min + (size_t)((r + 1) % 3u) * P.nslots + q, kept);
+    }
+}
+
+// ------------------------------------------------------------ host-stepped
+
+__global__ void __launch_bounds__(1024) k_relax(VorParams P) {
+    __shared__ WaveScratch s_wave[MAX_WAVES];
+    if (ld_agent(&P.pass->all_done)) return;
+    const uint32_t r = ld_agent(&P.pass->round);
+    const RoundIdx R = round_idx(r);
+    const uint32_t cs = min(ld_agent(&P.cnt->s[r % 3u]), P.cap_s), cb = min(ld_agent(&P.cnt->b[r % 3u]), P.cap_b);
+    const uint32_t wpb = blockDim.x / 64, w = threadIdx.x / 64;
+    relax_round_body(P, R, P.slot.thr, cs, cb, &s_wave[w], blockIdx.x * wpb + w, gridDim.x * wpb);
+}
+
+__global__ void __launch_bounds__(256) k_control(VorParams P) {
+    __shared__ int s_adv, s_act;
+    if (P.pass->all_done) return;
+    const uint32_t r = P.pass->round;
+    if (threadIdx.x == 0) { s_adv = 0; s_act = 0; }
+    __syncthreads();
+    bool aa = false, act = false;
+    const uint32_t nb = (r + 1) % 3u;
+    for (uint32_t q = threadIdx.x; q < P.nslots; q += blockDim.x) {
+        decide_slot(P, r, q, P.slot.thr, P.slot.thr_prev, P.slot.carry, P.slot.active, P.slot.adv, P.slot.done,
+                    P.slot.advances, aa, act);
+        P.near_mark[(size_t)nb * P.nslots + q] = 0;
+        P.far_min[(size_t)nb * P.nslots + q] = DIST_INF;
+    }
+    if (aa) atomicOr(&s_adv, 1);
+    if (act) atomicOr(&s_act, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        P.cnt->s[(r + 2) % 3u] = 0;
+        P.cnt->b[(r + 2) % 3u] = 0;
+        P.pass->any_adv = s_adv;
+        if (!s_act) P.pass->all_done = 1;
+        P.pass->round = r + 1;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_advance(VorParams P) {
+    if (!ld_agent(&P.pass->any_adv)) return;
+    const uint32_t r = ld_agent(&P.pass->round) - 1;
+    const uint32_t wpb = blockDim.x / 64, w = threadIdx.x / 64;
+    advance_body(P, r, P.slot.thr, P.slot.thr_prev, P.slot.adv, blockIdx.x * wpb + w, gridDim.x * wpb);
+}
+
+// ---------------------------------------------------------------- persistent
+
+// Sense-counting grid barrier for a cooperative launch.  Gives up after a
+// bounded spin (then every workgroup leaves the kernel).
+DEVI bool grid_barrier(Counters *cn, uint32_t nblocks, PassCtl *pass, int *s_abort) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t g = __hip_atomic_load(&cn->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t arrived =
+            __hip_atomic_fetch_add(&cn->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        int ab = 0;
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&cn->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&cn->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&cn->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1u << 25) ||
+                    __hip_atomic_load(&cn->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    atomicOr(&pass->err, ERR_BARRIER_TIMEOUT);
+                    atomicExch(&cn->abort, 1u);
+                    ab = 1;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        *s_abort = ab;
+    }
+    __syncthreads();
+    return *s_abort == 0;
+}
+
+__global__ void __launch_bounds__(1024) k_persistent(VorParams P, uint32_t max_rounds) {
+    __shared__ WaveScratch s_wave[MAX_WAVES];
+    __shared__ uint64_t s_thr[PERSIST_SLOTS], s_thr_prev[PERSIST_SLOTS];
+    __shared__ uint32_t s_carry[PERSIST_SLOTS], s_active[PERSIST_SLOTS], s_adv[PERSIST_SLOTS];
+    __shared__ uint32_t s_done[PERSIST_SLOTS], s_advances[PERSIST_SLOTS];
+    __shared__ int s_abort, s_any_adv, s_any_act;
+    const uint32_t ns = P.nslots;
+    for (uint32_t q = threadIdx.x; q < ns; q += blockDim.x) {
+        s_thr[q] = P.slot.thr[q];
+        s_thr_prev[q] = P.slot.thr_prev[q];
+        s_carry[q] = P.slot.carry[q];
+        s_active[q] = P.slot.active[q];
+        s_adv[q] = 0;
+        s_done[q] = P.slot.done[q];
+        s_advances[q] = P.slot.advances[q];
+    }
+    __syncthreads();
+    if (P.pass->all_done) return;
+    uint32_t r = P.pass->round;
+    const uint32_t wpb = blockDim.x / 64, w = threadIdx.x / 64;
+    const uint32_t wave_gid = blockIdx.x * wpb + w, nwaves = gridDim.x * wpb;
+    bool finished = false, ok = true;
+    for (uint32_t it = 0; it < max_rounds; it++) {
+        const RoundIdx R = round_idx(r);
+        const uint32_t cs = min(ld_agent(&P.cnt->s[r % 3u]), P.cap_s);
+        const uint32_t cb = min(ld_agent(&P.cnt->b[r % 3u]), P.cap_b);
+        relax_round_body(P, R, s_thr, cs, cb, &s_wave[w], wave_gid, nwaves);
+        if (blockIdx.x == 0) {
+            const uint32_t nb = (r + 1) % 3u;
+            for (uint32_t q = threadIdx.x; q < ns; q += blockDim.x) {
+                P.near_mark[(size_t)nb * ns + q] = 0;
+                P.far_min[(size_t)nb * ns + q] = DIST_INF;
+            }
+            if (threadIdx.x == 0) {
+                P.cnt->s[(r + 2) % 3u] = 0;
+                P.cnt->b[(r + 2) % 3u] = 0;
+            }
+        }
+        if (!(ok = grid_barrier(P.cnt, gridDim.x, P.pass, &s_abort))) break;
+        if (threadIdx.x == 0) { s_any_adv = 0; s_any_act = 0; }
+        __syncthreads();
+        bool aa = false, act = false;
+        for (uint32_t q = threadIdx.x; q < ns; q += blockDim.x)
+            decide_slot(P, r, q, s_thr, s_thr_prev, s_carry, s_active, s_adv, s_done, s_advances, aa, act);
+        if (aa) atomicOr(&s_any_adv, 1);
+        if (act) atomicOr(&s_any_act, 1);
+        __syncthreads();
+        const bool any_adv = s_any_adv != 0, any_act = s_any_act != 0;
+        if (any_adv) {
+            advance_body(P, r, s_thr, s_thr_prev, s_adv, wave_gid, nwaves);
+            if (!(ok = grid_barrier(P.cnt, gridDim.x, P.pass, &s_abort))) break;
+        }
+        r++;
+        if (!any_act) {
+            finished = true;
+            break;
+        }
+    }
+    if (blockIdx.x == 0) {
+        for (uint32_t q = threadIdx.x; q < ns; q += blockDim.x) {
+            P.slot.thr[q] = s_thr[q];
+            P.slot.thr_prev[q] = s_thr_prev[q];
+            P.slot.carry[q] = s_carry[q];
+            P.slot.active[q] = s_active[q];
+            P.slot.adv[q] = 0;
+            P.slot.done[q] = s_done[q];
+            P.slot.advances[q] = s_advances[q];
+        }
+        if (threadIdx.x == 0) {
+            P.pass->round = r;
+            if (finished) P.pass->all_done = 1;
+            (void)ok;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ set-up
+
+template <typename T>
+__global__ void k_fill(T *p, uint64_t count, T value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_pass_reset(VorParams P) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        P.pass->round = 0;
+        P.pass->all_done = 1;  // no active query yet
+        P.pass->any_adv = 0;
+        P.pass->err = 0;
+        for (int i = 0; i < 3; i++) { P.cnt->s[i] = 0; P.cnt->b[i] = 0; }
+        P.cnt->bar_count = 0;
+        P.cnt->bar_gen = 0;
+        P.cnt->abort = 0;
+    }
+    for (uint32_t q = t; q < P.nslots; q += gridDim.x * blockDim.x) {
+        for (int b = 0; b < 3; b++) {
+            P.far_min[(size_t)b * P.nslots + q] = DIST_INF;
+            P.near_mark[(size_t)b * P.nslots + q] = 0;
+        }
+        P.slot.active[q] = 0;
+        P.slot.done[q] = 0;
+        P.slot.adv[q] = 0;
+        P.slot.advances[q] = 0;
+        P.slot.carry[q] = DIST_INF;
+        P.slot.thr[q] = 0;
+        P.slot.thr_prev[q] = 0;
+    }
+}
+
+// Per-vertex state of one query: keys unreached, stamps and marks clear.
+__global__ void k_slot_clear(uint64_t *key, uint32_t *aux, uint8_t *dirty, uint32_t n, uint32_t *heavy_pe,
+                             uint32_t nheavy) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        key[v] = KEY_INF;
+        aux[v] = 0;
+        dirty[v] = 0;
+    }
+    for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < nheavy; h += gridDim.x * blockDim.x)
+        heavy_pe[h] = NONE;
+}
+
+// Seeds of one query (sorted, distinct; seed index = position) become the
+// cells' roots (Alg. 3 initialisation) and the frontier of the current round.
+__global__ void k_slot_seed(VorParams P, uint32_t slot, const uint32_t *seeds, uint32_t k) {
+    const uint32_t r = P.pass->round;
+    const RoundIdx R = round_idx(r);
+    const uint32_t n = P.g.n;
+    for (uint32_t i = threadIdx.x; i < k; i += blockDim.x) {
+        const uint32_t v = seeds[i];
+        P.key[(size_t)slot * n + v] = (uint64_t)i;  // dist 0, seed index i
+        P.aux[(size_t)slot * n + v] = r;
+        const uint32_t deg = P.g.rp[v + 1] - P.g.rp[v];
+        if (deg <= P.small_max) {
+            const uint32_t pos = atomicAdd(&P.cnt->s[r % 3u], 1u);
+            if (pos < P.cap_s) P.items_s[R.cur][pos] = s_item(slot, v);
+            else atomicOr(&P.pass->err, ERR_LIST_OVERFLOW);
+        } else {
+            const uint32_t nch = (deg + P.chunk - 1) / P.chunk;
+            const uint32_t pos = atomicAdd(&P.cnt->b[r % 3u], nch);
+            for (uint32_t c = 0; c < nch; c++) {
+                if (pos + c < P.cap_b) P.items_b[R.cur][pos + c] = b_item(slot, c, v);
+                else { atomicOr(&P.pass->err, ERR_LIST_OVERFLOW); break; }
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        P.slot.thr[slot] = P.delta == 0xFFFFFFFFu ? ~0ull : (uint64_t)P.delta;
+        P.slot.thr_prev[slot] = 0;
+        P.slot.carry[slot] = DIST_INF;
+        P.slot.active[slot] = 1;
+        P.slot.adv[slot] = 0;
+        P.slot.done[slot] = 0;
+        P.slot.advances[slot] = 0;
+        for (int b = 0; b < 3; b++) {
+            P.far_min[(size_t)b * P.nslots + slot] = DIST_INF;
+            P.near_mark[(size_t)b * P.nslots + slot] = 0;
+        }
+        P.pass->all_done = 0;
+    }
+}
+
+// ------------------------------------------------- pred + boundary scan
+
+struct ScanWave {
+    uint32_t incl[64];
+    uint32_t beg[64];
+    uint32_t row[64];
+    uint32_t found[64];
+    uint64_t key[64];
+};
+
+DEVI uint64_t pair_index(uint32_t i, uint32_t j) {  // i < j
+    return (uint64_t)j * (j - 1) / 2 + i;
+}
+
+// Cross-cell candidate of the half edge row -> u (row < u) at CSR offset e.
+DEVI void set_err(uint32_t *err, uint32_t bit) {
+    if (!(*err & bit)) atomicOr(err, bit);
+}
+
+DEVI void boundary_candidate(uint64_t *pt, uint32_t *err, uint64_t krow, uint64_t ku, uint32_t w, uint32_t e) {
+    const uint32_t i1 = (uint32_t)krow, i2 = (uint32_t)ku;
+    if (i1 == i2) return;
+    const uint64_t bsum = (krow >> 32) + (uint64_t)w + (ku >> 32);
+    if (bsum >= (1ull << 32)) {
+        set_err(err, ERR_SUM_OVERFLOW);
+        return;
+    }
+    const uint64_t val = (bsum << 32) | e;
+    uint64_t *p = pt + pair_index(min(i1, i2), max(i1, i2));
+    if (val < *p) atomicMin((unsigned long long *)p, (unsigned long long)val);
+}
+
+DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *pred, uint64_t *pt, uint32_t *err,
+                           uint32_t grp, ScanWave *L) {
+    const uint32_t n = S.g.n, ln = lane();
+    const uint32_t row = grp * 64 + ln;
+    uint64_t kv = KEY_INF;
+    uint32_t beg = 0, deg = 0, found = 1;
+    if (row < n) {
+        kv = key[row];
+        const uint32_t b0 = S.g.rp[row], d0 = S.g.rp[row + 1] - b0;
+        if (d0 <= S.g.scan_heavy) {
+            if (kv == KEY_INF) {
+                pred[row] = NONE;
+            } else {
+                beg = b0;
+                deg = d0;
+                if ((kv >> 32) == 0) pred[row] = row;  // a seed is its own predecessor
+                else found = 0;
+            }
+        }
+    }
+    const uint32_t incl = wave_incl_scan(deg);
+    const uint32_t total = __shfl(incl, 63, 64);
+    L->incl[ln] = incl;
+    L->beg[ln] = beg;
+    L->row[ln] = row;
+    L->found[ln] = found;
+    L->key[ln] = kv;
+    wave_sync();
+    for (uint32_t base = 0; base < total; base += 64) {
+        const uint32_t t = base + ln;
+        const bool valid = t < total;
+        uint32_t j = 0;
+        if (valid) {
+            uint32_t lo = 0, hi = 63;
+            while (lo < hi) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (L->incl[mid] > t) hi = mid; else lo = mid + 1;
+            }
+            j = lo;
+        }
+        const uint32_t ex = j ? L->incl[j - 1] : 0;
+        const uint32_t e = L->beg[j] + (t - ex);
+        const uint64_t kr = L->key[j];
+        const uint32_t rj = L->row[j];
+        uint32_t u = 0, w = 0;
+        uint64_t ku = KEY_INF;
+        if (valid) {
+            const uint2 a = S.g.adj[e];
+            u = a.x;
+            w = a.y;
+            ku = key[u];
+            if (ku == KEY_INF) set_err(err, ERR_DIST_OVERFLOW);
+        }
+        const bool q = valid && !L->found[j] && ku != KEY_INF && (uint32_t)ku == (uint32_t)kr &&
+                       (ku >> 32) + w == (kr >> 32);
+        const uint64_t mq = __ballot(q);
+        // lanes of row j in this step start at lane sj; the first qualifying one wins
+        const uint32_t sj = ex > base ? ex - base : 0;
+        const uint64_t earlier = mq & ((1ull << ln) - 1ull) & ~((1ull << sj) - 1ull);
+        if (q && earlier == 0) {
+            pred[rj] = u;
+            L->found[j] = 1;
+        }
+        if (valid && rj < u && ku != KEY_INF) boundary_candidate(pt, err, kr, ku, w, e);
+        wave_sync();
+    }
+}
+
+DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *pt, uint32_t *err,
+                           uint32_t *heavy_pe, uint32_t lc) {
+    // heavy row h owning chunk lc: largest h with heavy_chunk_off[h] <= lc
+    uint32_t lo = 0, hi = S.g.nheavy;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (S.g.heavy_chunk_off[mid] <= lc) lo = mid; else hi = mid;
+    }
+    const uint32_t h = lo, row = S.g.heavy_rows[h];
+    const uint32_t c = lc - S.g.heavy_chunk_off[h];
+    const uint64_t kv = key[row];
+    if (kv == KEY_INF) return;
+    const uint32_t beg = S.g.rp[row] + c * S.g.scan_chunk;
+    const uint32_t lim = S.g.rp[row + 1];
+    const uint32_t end = (lim - beg > S.g.scan_chunk) ? beg + S.g.scan_chunk : lim;
+    const bool is_seed = (kv >> 32) == 0;
+    uint32_t best = NONE;
+    for (uint32_t e0 = beg; e0 < end; e0 += 64) {
+        const uint32_t e = e0 + lane();
+        if (e < end) {
+            const uint2 a = S.g.adj[e];
+            const uint64_t ku = key[a.x];
+            if (ku == KEY_INF) {
+                set_err(err, ERR_DIST_OVERFLOW);
+            } else {
+                if (!is_seed && best == NONE && (uint32_t)ku == (uint32_t)kv && (ku >> 32) + a.y == (kv >> 32))
+                    best = e;
+                if (row < a.x) boundary_candidate(pt, err, kv, ku, a.y, e);
+            }
+        }
+    }
+    best = wave_min(best);
+    if (lane() == 0 && best != NONE) atomicMin(heavy_pe + h, best);
+}
+
+__global__ void __launch_bounds__(256) k_scan(ScanParams S) {
+    __shared__ ScanWave s_wave[4];
+    const uint32_t n = S.g.n;
+    const uint32_t wpb = blockDim.x / 64, w = threadIdx.x / 64;
+    const uint64_t nwaves = (uint64_t)gridDim.x * wpb;
+    const uint32_t ngroups = (n + 63) / 64;
+    const uint64_t per_slot = (uint64_t)ngroups + S.g.nheavy_chunks;
+    const uint64_t units = per_slot * S.nscan;
+    for (uint64_t u = (uint64_t)blockIdx.x * wpb + w; u < units; u += nwaves) {
+        const uint32_t si = (uint32_t)(u / per_slot);
+        const uint32_t lu = (uint32_t)(u % per_slot);
+        const uint32_t slot = S.slot_ids[si];
+        const uint64_t *key = S.key + (size_t)slot * n;
+        uint64_t *pt = S.pt[slot];
+        uint32_t *err = S.slot_err + slot;
+        if (lu < ngroups)
+            scan_light_group(S, key, S.aux + (size_t)slot * n, pt, err, lu, &s_wave[w]);
+        else
+            scan_heavy_chunk(S, key, pt, err, S.heavy_pe + (size_t)slot * S.g.nheavy, lu - ngroups);
+    }
+}
+
+// pred of heavy rows from the smallest qualifying CSR offset.
+__global__ void k_scan_heavy_pred(ScanParams S) {
+    const uint32_t n = S.g.n, nh = S.g.nheavy;
+    const uint64_t total = (uint64_t)nh * S.nscan;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t slot = S.slot_ids[t / nh], h = (uint32_t)(t % nh);
+        const uint32_t row = S.g.heavy_rows[h];
+        const uint64_t kv = S.key[(size_t)slot * n + row];
+        uint32_t p;
+        if (kv == KEY_INF) p = NONE;
+        else if ((kv >> 32) == 0) p = row;
+        else {
+            const uint32_t e = S.heavy_pe[(size_t)slot * nh + h];
+            p = e == NONE ? NONE : S.g.adj[e].x;
+        }
+        S.aux[(size_t)slot * n + row] = p;
+    }
+}
+
+// --------------------------------------------------------- G'1 compaction
+
+__global__ void __launch_bounds__(256) k_compact(CompactParams C) {
+    const uint32_t wpb = blockDim.x / 64, w = threadIdx.x / 64;
+    const uint64_t wave_gid = (uint64_t)blockIdx.x * wpb + w, nwaves = (uint64_t)gridDim.x * wpb;
+    for (uint32_t si = 0; si < C.nscan; si++) {
+        const uint32_t slot = C.slot_ids[si];
+        const uint64_t *pt = C.pt[slot];
+        const uint64_t len = C.pt_len[slot];
+        for (uint64_t base = wave_gid * 64; base < len; base += nwaves * 64) {
+            const uint64_t i = base + lane();
+            const uint64_t val = i < len ? pt[i] : KEY_INF;
+            const bool keep = val != KEY_INF;
+            const uint64_t m = __ballot(keep);
+            if (m == 0) continue;
+            const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1;
+            uint32_t pos0 = 0;
+            if (lane() == leader) pos0 = atomicAdd(&C.out_cnt[slot], (uint32_t)__popcll(m));
+            pos0 = __shfl(pos0, leader, 64);
+            if (keep) {
+                const uint32_t pos = pos0 + lanes_below(m);
+                if (pos < C.out_cap[slot]) {
+                    C.out_idx[slot][pos] = (uint32_t)i;
+                    C.out_val[slot][pos] = val;
+                } else {
+                    atomicOr(&C.pass->err, ERR_LIST_OVERFLOW);
+                }
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------- expansion
+
+DEVI void emit_edge(const ExpandParams &E, uint32_t x, uint32_t y, uint32_t w) {
+    const uint32_t pos = atomicAdd(E.ocnt, 1u);
+    if (pos < E.g.n) {
+        E.oa[pos] = min(x, y);
+        E.ob[pos] = max(x, y);
+        E.ow[pos] = w;
+    }
+}
+
+// Alg. 6: every kept cross-cell edge plus the predecessor paths of both its
+// endpoints up to their seeds; a visited bit makes each path edge appear once.
+__global__ void k_expand(ExpandParams E) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E.nsel) return;
+    const uint32_t e = E.sel_e[t];
+    uint32_t lo = 0, hi = E.g.n;  // rp[lo] <= e < rp[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (E.g.rp[mid] <= e) lo = mid; else hi = mid;
+    }
+    const uint2 a = E.g.adj[e];
+    emit_edge(E, lo, a.x, a.y);
+    uint32_t ends[2] = {lo, a.x};
+    for (int s = 0; s < 2; s++) {
+        uint32_t x = ends[s];
+        for (uint32_t steps = 0; steps < E.g.n; steps++) {
+            const uint64_t kx = E.key[x];
+            if ((kx >> 32) == 0) break;  // reached the seed
+            const uint32_t bit = 1u << (x & 31);
+            if (atomicOr(E.visited + (x >> 5), bit) & bit) break;  // another walk owns the rest
+            const uint32_t p = E.pred[x];
+            if (p >= E.g.n) break;  // cannot happen for a converged pass; keeps the walk in bounds
+            const uint64_t kp = E.key[p];
+            emit_edge(E, x, p, (uint32_t)((kx >> 32) - (kp >> 32)));
+            x = p;
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+static uint32_t fill_grid(uint64_t count) {
+    uint64_t g = (count + 255) / 256;
+    return (uint32_t)(g < 4096 ? (g ? g : 1) : 4096);
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t count, uint64_t value, hipStream_t s) {
+    if (!count) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<uint64_t>, dim3(fill_grid(count)), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t s) {
+    if (!count) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(fill_grid(count)), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u8(uint8_t *p, uint64_t count, uint8_t value, hipStream_t s) {
+    if (!count) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<uint8_t>, dim3(fill_grid(count)), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_reset(const VorParams &P, hipStream_t s) {
+    hipLaunchKernelGGL(k_pass_reset, dim3((P.nslots + 255) / 256), dim3(256), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_start(const VorParams &P, uint32_t slot, const uint32_t *d_seeds, uint32_t k,
+                             uint32_t *heavy_pe_slot, uint32_t nheavy, hipStream_t s) {
+    const uint32_t n = P.g.n;
+    hipLaunchKernelGGL(k_slot_clear, dim3(fill_grid(n)), dim3(256), 0, s, P.key + (size_t)slot * n,
+                       P.aux + (size_t)slot * n, P.dirty + (size_t)slot * n, n, heavy_pe_slot, nheavy);
+    hipLaunchKernelGGL(k_slot_seed, dim3(1), dim3(256), 0, s, P, slot, d_seeds, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_round(const VorParams &P, uint32_t grid, uint32_t block, hipStream_t s) {
+    hipLaunchKernelGGL(k_relax, dim3(grid), dim3(block), 0, s, P);
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(k_advance, dim3(grid), dim3(block), 0, s, P);
+    return hipGetLastError();
+}
+
+int persistent_max_grid(uint32_t block) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent, (int)block, 0) != hipSuccess) return 0;
+    return per_cu * prop.multiProcessorCount;
+}
+
+hipError_t launch_persistent(const VorParams &P, uint32_t grid, uint32_t block, uint32_t max_rounds,
+                             hipStream_t s) {
+    if (P.nslots > PERSIST_SLOTS) return hipErrorInvalidValue;
+    VorParams p = P;
+    void *args[] = {&p, &max_rounds};
+    return hipLaunchCooperativeKernel((const void *)k_persistent, dim3(grid), dim3(block), args, 0, s);
+}
+
+hipError_t launch_scan(const ScanParams &S, uint32_t grid, uint32_t block, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan, dim3(grid), dim3(block), 0, s, S);
+    if (S.g.nheavy) {
+        const uint64_t t = (uint64_t)S.g.nheavy * S.nscan;
+        hipLaunchKernelGGL(k_scan_heavy_pred, dim3(fill_grid(t)), dim3(256), 0, s, S);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const CompactParams &C, uint32_t grid, uint32_t block, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact, dim3(grid), dim3(block), 0, s, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand(const ExpandParams &E, hipStream_t s) {
+    if (!E.nsel) return hipSuccess;
+    hipLaunchKernelGGL(k_expand, dim3((E.nsel + 127) / 128), dim3(128), 0, s, E);
+    return hipGetLastError();
+}
+
+}  // namespace stn

@@ -1,0 +1,403 @@
+// One multi-query pass over a resident graph: Alg. 2 Steps 1-7 for every
+// query of the batch, sharing the relaxation rounds and the boundary scan.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <tuple>
+
+#include "engine.h"
+
+namespace stn {
+
+uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chunk) {
+    uint64_t t = 0;
+    for (uint32_t v = 0; v < g->n; v++) {
+        uint64_t d = g->h_rp[v + 1] - g->h_rp[v];
+        if (d > small_max) t += (d + chunk - 1) / chunk;
+    }
+    return t;
+}
+
+namespace {
+
+struct Layout {
+    size_t counters, pass, thr, thr_prev, pt_ptr, pt_len, oidx_ptr, oval_ptr, ocap, far_min, near_mark, carry, active,
+        adv, done, advances, slot_err, out_cnt, slot_ids, total;
+    explicit Layout(uint32_t Q) {
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+            size_t at = o;
+            o += (bytes + 255) & ~(size_t)255;
+            return at;
+        };
+        counters = take(sizeof(Counters));
+        pass = take(sizeof(PassCtl));
+        thr = take(8ull * Q);
+        thr_prev = take(8ull * Q);
+        pt_ptr = take(8ull * Q);
+        pt_len = take(8ull * Q);
+        oidx_ptr = take(8ull * Q);
+        oval_ptr = take(8ull * Q);
+        ocap = take(8ull * Q);
+        far_min = take(12ull * Q);
+        near_mark = take(12ull * Q);
+        carry = take(4ull * Q);
+        active = take(4ull * Q);
+        adv = take(4ull * Q);
+        done = take(4ull * Q);
+        advances = take(4ull * Q);
+        slot_err = take(4ull * Q);
+        out_cnt = take(4ull * Q);
+        slot_ids = take(4ull * Q);
+        total = o;
+    }
+};
+
+struct Timer {
+    bool on;
+    hipStream_t s;
+    std::vector<hipEvent_t> ev;
+    Timer(bool on_, hipStream_t s_) : on(on_), s(s_) {}
+    void mark() {
+        if (!on) return;
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+        (void)hipEventRecord(e, s);
+        ev.push_back(e);
+    }
+    double ms(size_t a, size_t b) {
+        if (!on || b >= ev.size()) return 0.0;
+        float m = 0.f;
+        (void)hipEventSynchronize(ev[b]);
+        (void)hipEventElapsedTime(&m, ev[a], ev[b]);
+        return m;
+    }
+    ~Timer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
+    const auto t_start = std::chrono::steady_clock::now();
+    hipStream_t st = g->stream;
+    Workspace &ws = g->ws;
+    const uint32_t n = g->n;
+    int rc;
+
+    // Queries that need the device: status OK and at least two seeds.
+    std::vector<uint32_t> act;
+    for (uint32_t i = 0; i < qs.size(); i++) {
+        if (qs[i].status) continue;
+        if (qs[i].S.size() < 2) {  // k == 1: empty tree, D = 0
+            qs[i].result.reset(new steiner_result());
+            continue;
+        }
+        act.push_back(i);
+    }
+    const uint32_t Q = (uint32_t)act.size();
+    if (Q == 0) return STEINER_OK;
+
+    // ---------------------------------------------------------- allocation
+    const uint64_t cap_s = (uint64_t)Q * n + 64;
+    const uint64_t cap_b = (uint64_t)Q * big_row_chunks(g, o.small_max, o.chunk) + 64;
+    if (cap_s >= (1ull << 32) || cap_b >= (1ull << 32))
+        return fail(STEINER_ENOMEM, "batch too large for 32-bit frontier counters");
+    std::vector<uint64_t> pt_off(Q + 1, 0), oc_off(Q + 1, 0), sd_off(Q + 1, 0);
+    uint64_t half = g->nnz / 2 + 1;
+    for (uint32_t s = 0; s < Q; s++) {
+        const uint64_t k = qs[act[s]].S.size();
+        const uint64_t P = k * (k - 1) / 2;
+        pt_off[s + 1] = pt_off[s] + P;
+        oc_off[s + 1] = oc_off[s] + std::min(P, half);
+        sd_off[s + 1] = sd_off[s] + k;
+    }
+    const Layout L(Q);
+    const size_t QN = (size_t)Q * n;
+    if ((rc = ws.key.ensure(QN * 8)) || (rc = ws.aux.ensure(QN * 4)) || (rc = ws.dirty.ensure(QN)) ||
+        (rc = ws.items_s[0].ensure(cap_s * 8)) || (rc = ws.items_s[1].ensure(cap_s * 8)) ||
+        (rc = ws.items_b[0].ensure(cap_b * 8)) || (rc = ws.items_b[1].ensure(cap_b * 8)) ||
+        (rc = ws.ctl.ensure(L.total)) || (rc = ws.heavy_pe.ensure((size_t)Q * g->nheavy * 4 + 4)) ||
+        (rc = ws.seeds.ensure(sd_off[Q] * 4)) || (rc = ws.pt.ensure(pt_off[Q] * 8)) ||
+        (rc = ws.cidx.ensure(oc_off[Q] * 4)) || (rc = ws.cval.ensure(oc_off[Q] * 8)) ||
+        (rc = ws.visited.ensure(((size_t)n + 31) / 32 * 4)) || (rc = ws.oedges.ensure((size_t)n * 12 + 16)) ||
+        (rc = ws.host.ensure(std::max<size_t>(L.total, sd_off[Q] * 4) + 4096)))
+        return rc;
+    uint8_t *ctl = ws.ctl.as<uint8_t>();
+    uint8_t *hctl = ws.host.as<uint8_t>();
+
+    VorParams P{};
+    P.g = g->dg;
+    P.key = ws.key.as<uint64_t>();
+    P.aux = ws.aux.as<uint32_t>();
+    P.dirty = ws.dirty.as<uint8_t>();
+    P.items_s[0] = ws.items_s[0].as<uint64_t>();
+    P.items_s[1] = ws.items_s[1].as<uint64_t>();
+    P.items_b[0] = ws.items_b[0].as<uint64_t>();
+    P.items_b[1] = ws.items_b[1].as<uint64_t>();
+    P.cap_s = (uint32_t)cap_s;
+    P.cap_b = (uint32_t)cap_b;
+    P.cnt = (Counters *)(ctl + L.counters);
+    P.pass = (PassCtl *)(ctl + L.pass);
+    P.far_min = (uint32_t *)(ctl + L.far_min);
+    P.near_mark = (uint32_t *)(ctl + L.near_mark);
+    P.slot.thr = (uint64_t *)(ctl + L.thr);
+    P.slot.thr_prev = (uint64_t *)(ctl + L.thr_prev);
+    P.slot.carry = (uint32_t *)(ctl + L.carry);
+    P.slot.active = (uint32_t *)(ctl + L.active);
+    P.slot.adv = (uint32_t *)(ctl + L.adv);
+    P.slot.done = (uint32_t *)(ctl + L.done);
+    P.slot.advances = (uint32_t *)(ctl + L.advances);
+    P.nslots = Q;
+    P.delta = o.delta;
+    P.small_max = o.small_max;
+    P.chunk = o.chunk;
+
+    // Per-slot pointer tables (host image, then one copy).
+    {
+        uint64_t *h_ptr = (uint64_t *)(hctl + L.pt_ptr);
+        uint64_t *h_len = (uint64_t *)(hctl + L.pt_len);
+        uint64_t *h_oi = (uint64_t *)(hctl + L.oidx_ptr);
+        uint64_t *h_ov = (uint64_t *)(hctl + L.oval_ptr);
+        uint64_t *h_oc = (uint64_t *)(hctl + L.ocap);
+        uint32_t *h_ids = (uint32_t *)(hctl + L.slot_ids);
+        for (uint32_t s = 0; s < Q; s++) {
+            h_ptr[s] = (uint64_t)(uintptr_t)(ws.pt.as<uint64_t>() + pt_off[s]);
+            h_len[s] = pt_off[s + 1] - pt_off[s];
+            h_oi[s] = (uint64_t)(uintptr_t)(ws.cidx.as<uint32_t>() + oc_off[s]);
+            h_ov[s] = (uint64_t)(uintptr_t)(ws.cval.as<uint64_t>() + oc_off[s]);
+            h_oc[s] = oc_off[s + 1] - oc_off[s];
+            h_ids[s] = s;
+        }
+        memset(hctl + L.slot_err, 0, 4ull * Q);
+        memset(hctl + L.out_cnt, 0, 4ull * Q);
+        if ((rc = hip_check(hipMemcpyAsync(ctl + L.pt_ptr, hctl + L.pt_ptr, L.far_min - L.pt_ptr, hipMemcpyHostToDevice, st),
+                            "H2D tables")))
+            return rc;
+        if ((rc = hip_check(hipMemcpyAsync(ctl + L.slot_err, hctl + L.slot_err, L.total - L.slot_err,
+                                           hipMemcpyHostToDevice, st), "H2D tables")))
+            return rc;
+        if ((rc = hip_check(hipStreamSynchronize(st), "tables"))) return rc;
+    }
+    // Seeds of every slot, concatenated.
+    {
+        uint32_t *hs = ws.host.as<uint32_t>();
+        for (uint32_t s = 0; s < Q; s++)
+            memcpy(hs + sd_off[s], qs[act[s]].S.data(), qs[act[s]].S.size() * 4);
+        if ((rc = hip_check(hipMemcpyAsync(ws.seeds.ptr, hs, sd_off[Q] * 4, hipMemcpyHostToDevice, st), "H2D seeds")))
+            return rc;
+        if ((rc = hip_check(hipStreamSynchronize(st), "seeds"))) return rc;
+    }
+
+    Timer tm(o.timing, st);
+    tm.mark();  // 0
+    if ((rc = hip_check(launch_pass_reset(P, st), "pass reset"))) return rc;
+    if ((rc = hip_check(launch_fill_u64(ws.pt.as<uint64_t>(), pt_off[Q], KEY_INF, st), "pair table init"))) return rc;
+    for (uint32_t s = 0; s < Q; s++) {
+        rc = hip_check(launch_slot_start(P, s, ws.seeds.as<uint32_t>() + sd_off[s], (uint32_t)qs[act[s]].S.size(),
+                                         ws.heavy_pe.as<uint32_t>() + (size_t)s * g->nheavy, g->nheavy, st),
+                       "slot start");
+        if (rc) return rc;
+    }
+    tm.mark();  // 1
+
+    // ------------------------------------------------- Step 1: Voronoi cells
+    PassCtl *hpass = (PassCtl *)(hctl + L.pass);
+    const uint32_t round_cap = 1u << 26;
+    const uint32_t rounds_per_launch = 4096;
+    const double wall_cap_s = 120.0;
+    auto wall = [&]() {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    };
+    bool persistent = o.driver == 2 && Q <= 256;
+    uint32_t pgrid = 0;
+    if (persistent) {
+        int mg = persistent_max_grid(o.block);
+        pgrid = std::min<uint32_t>(o.grid, (uint32_t)std::max(mg, 0));
+        if (pgrid == 0) persistent = false;
+    }
+    if (persistent) {
+        for (;;) {
+            if ((rc = hip_check(launch_persistent(P, pgrid, o.block, rounds_per_launch, st), "persistent pass")))
+                return rc;
+            if ((rc = hip_check(hipMemcpyAsync(hpass, P.pass, sizeof(PassCtl), hipMemcpyDeviceToHost, st), "D2H pass")))
+                return rc;
+            if ((rc = hip_check(hipStreamSynchronize(st), "persistent sync"))) return rc;
+            if (hpass->err & (ERR_LIST_OVERFLOW | ERR_BARRIER_TIMEOUT))
+                return fail(STEINER_EDEVICE, "relaxation pass failed (err bits 0x%x)", hpass->err);
+            if (hpass->all_done) break;
+            if (hpass->round >= round_cap || wall() > wall_cap_s)
+                return fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)", hpass->round);
+        }
+    } else {
+        uint32_t chunk_rounds = 4, launched = 0;
+        for (;;) {
+            for (uint32_t i = 0; i < chunk_rounds; i++)
+                if ((rc = hip_check(launch_round(P, o.grid, o.block, st), "round"))) return rc;
+            launched += chunk_rounds;
+            if ((rc = hip_check(hipMemcpyAsync(hpass, P.pass, sizeof(PassCtl), hipMemcpyDeviceToHost, st), "D2H pass")))
+                return rc;
+            if ((rc = hip_check(hipStreamSynchronize(st), "round sync"))) return rc;
+            if (hpass->err & ERR_LIST_OVERFLOW) return fail(STEINER_EDEVICE, "frontier overflow");
+            if (hpass->all_done) break;
+            if (launched >= round_cap || wall() > wall_cap_s)
+                return fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)", hpass->round);
+            chunk_rounds = std::min<uint32_t>(chunk_rounds * 2, 64);
+        }
+    }
+    const uint32_t rounds = hpass->round;
+    tm.mark();  // 2
+
+    // ------------------------------ canonical pred + Step 2 boundary scan
+    ScanParams SP{};
+    SP.g = g->dg;
+    SP.key = P.key;
+    SP.aux = P.aux;
+    SP.heavy_pe = ws.heavy_pe.as<uint32_t>();
+    SP.pt = (uint64_t *const *)(ctl + L.pt_ptr);
+    SP.slot_ids = (const uint32_t *)(ctl + L.slot_ids);
+    SP.nscan = Q;
+    SP.slot_err = (uint32_t *)(ctl + L.slot_err);
+    const uint32_t sgrid = (uint32_t)std::max(1, g->cu_count) * 8;
+    if ((rc = hip_check(launch_scan(SP, sgrid, 256, st), "scan"))) return rc;
+    tm.mark();  // 3
+
+    // ------------------------------------------------- G'1 compaction
+    CompactParams CP{};
+    CP.pt = SP.pt;
+    CP.pt_len = (const uint64_t *)(ctl + L.pt_len);
+    CP.out_idx = (uint32_t *const *)(ctl + L.oidx_ptr);
+    CP.out_val = (uint64_t *const *)(ctl + L.oval_ptr);
+    CP.out_cap = (const uint64_t *)(ctl + L.ocap);
+    CP.out_cnt = (uint32_t *)(ctl + L.out_cnt);
+    CP.slot_ids = SP.slot_ids;
+    CP.nscan = Q;
+    CP.pass = P.pass;
+    if ((rc = hip_check(launch_compact(CP, sgrid, 256, st), "compact"))) return rc;
+    tm.mark();  // 4
+    // errors, counts, per-slot advances
+    if ((rc = hip_check(hipMemcpyAsync(hctl + L.advances, ctl + L.advances, L.total - L.advances, hipMemcpyDeviceToHost, st),
+                        "D2H counts")))
+        return rc;
+    if ((rc = hip_check(hipMemcpyAsync(hpass, P.pass, sizeof(PassCtl), hipMemcpyDeviceToHost, st), "D2H pass"))) return rc;
+    if ((rc = hip_check(hipStreamSynchronize(st), "compact sync"))) return rc;
+    if (hpass->err & ERR_LIST_OVERFLOW) return fail(STEINER_EDEVICE, "compaction overflow");
+    const uint32_t *h_err = (const uint32_t *)(hctl + L.slot_err);
+    const uint32_t *h_cnt = (const uint32_t *)(hctl + L.out_cnt);
+    const uint32_t *h_adv = (const uint32_t *)(hctl + L.advances);
+    std::vector<uint32_t> slot_err(h_err, h_err + Q), out_cnt(h_cnt, h_cnt + Q), slot_adv(h_adv, h_adv + Q);
+
+    // debug: key / pred of the single slot
+    for (uint32_t s = 0; s < Q; s++) {
+        Query &qq = qs[act[s]];
+        if (qq.want_key && !slot_err[s]) {
+            rc = hip_check(hipMemcpyAsync(qq.want_key, P.key + (size_t)s * n, (size_t)n * 8, hipMemcpyDeviceToHost, st), "D2H key");
+            if (!rc) rc = hip_check(hipMemcpyAsync(qq.want_pred, P.aux + (size_t)s * n, (size_t)n * 4, hipMemcpyDeviceToHost, st), "D2H pred");
+            if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H");
+            if (rc) return rc;
+        }
+    }
+
+    // ---------------------------------------- Steps 3-7 per query
+    double ms_mst = 0.0, ms_expand = 0.0;
+    for (uint32_t s = 0; s < Q; s++) {
+        Query &qq = qs[act[s]];
+        const uint32_t k = (uint32_t)qq.S.size();
+        if (slot_err[s] & (ERR_DIST_OVERFLOW | ERR_SUM_OVERFLOW)) {
+            qq.status = fail(STEINER_EOVERFLOW, "distance or cross-cell sum does not fit in 32 bits");
+            continue;
+        }
+        if (qq.stop_after == STOP_AFTER_SCAN) continue;
+        const uint32_t m = out_cnt[s];
+        qq.pidx.resize(m);
+        qq.pval.resize(m);
+        if (m) {
+            rc = hip_check(hipMemcpyAsync(qq.pidx.data(), ws.cidx.as<uint32_t>() + oc_off[s], (size_t)m * 4, hipMemcpyDeviceToHost, st), "D2H G'1");
+            if (!rc) rc = hip_check(hipMemcpyAsync(qq.pval.data(), ws.cval.as<uint64_t>() + oc_off[s], (size_t)m * 8, hipMemcpyDeviceToHost, st), "D2H G'1");
+            if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H G'1");
+            if (rc) return rc;
+        }
+        if (qq.stop_after == STOP_AFTER_COMPACT) continue;
+        const auto t0 = std::chrono::steady_clock::now();
+        std::vector<uint32_t> chosen;
+        int mrc = prim_mst(k, qq.pidx, qq.pval, chosen);
+        const auto t1 = std::chrono::steady_clock::now();
+        ms_mst += std::chrono::duration<double, std::milli>(t1 - t0).count();
+        if (mrc) {
+            qq.status = fail(mrc, "seeds are not connected");
+            continue;
+        }
+        // Step 4: the cross-cell edge kept for each MST pair; Steps 5-6 on the device.
+        std::vector<uint32_t> sel(chosen.size());
+        for (size_t t = 0; t < chosen.size(); t++) sel[t] = (uint32_t)(qq.pval[chosen[t]] & 0xFFFFFFFFu);
+        if ((rc = ws.sel.ensure(sel.size() * 4 + 4))) return rc;
+        uint32_t *oe = ws.oedges.as<uint32_t>();
+        ExpandParams EP{};
+        EP.g = g->dg;
+        EP.key = P.key + (size_t)s * n;
+        EP.pred = P.aux + (size_t)s * n;
+        EP.sel_e = ws.sel.as<uint32_t>();
+        EP.nsel = (uint32_t)sel.size();
+        EP.visited = ws.visited.as<uint32_t>();
+        EP.oa = oe;
+        EP.ob = oe + n;
+        EP.ow = oe + 2 * (size_t)n;
+        EP.ocnt = oe + 3 * (size_t)n;
+        rc = hip_check(hipMemcpyAsync(ws.sel.ptr, sel.data(), sel.size() * 4, hipMemcpyHostToDevice, st), "H2D sel");
+        if (!rc) rc = hip_check(launch_fill_u32(EP.visited, ((size_t)n + 31) / 32, 0u, st), "visited");
+        if (!rc) rc = hip_check(launch_fill_u32(EP.ocnt, 1, 0u, st), "count");
+        if (!rc) rc = hip_check(launch_expand(EP, st), "expand");
+        uint32_t m_out = 0;
+        if (!rc) rc = hip_check(hipMemcpyAsync(&m_out, EP.ocnt, 4, hipMemcpyDeviceToHost, st), "D2H count");
+        if (!rc) rc = hip_check(hipStreamSynchronize(st), "expand sync");
+        if (rc) return rc;
+        if (m_out > n) return fail(STEINER_EDEVICE, "expansion overflow");
+        std::unique_ptr<steiner_result> res(new steiner_result());
+        std::vector<uint32_t> a(m_out), b(m_out), w(m_out);
+        rc = hip_check(hipMemcpyAsync(a.data(), EP.oa, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+        if (!rc) rc = hip_check(hipMemcpyAsync(b.data(), EP.ob, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+        if (!rc) rc = hip_check(hipMemcpyAsync(w.data(), EP.ow, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+        if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H edges");
+        if (rc) return rc;
+        const auto t2 = std::chrono::steady_clock::now();
+        ms_expand += std::chrono::duration<double, std::milli>(t2 - t1).count();
+        // Step 7: canonical order (a, b, w) and D
+        std::vector<std::tuple<uint32_t, uint32_t, uint32_t>> ed(m_out);
+        for (uint32_t t = 0; t < m_out; t++) ed[t] = std::make_tuple(a[t], b[t], w[t]);
+        std::sort(ed.begin(), ed.end());
+        res->a.resize(m_out);
+        res->b.resize(m_out);
+        res->w.resize(m_out);
+        uint64_t D = 0;
+        for (uint32_t t = 0; t < m_out; t++) {
+            res->a[t] = std::get<0>(ed[t]);
+            res->b[t] = std::get<1>(ed[t]);
+            res->w[t] = std::get<2>(ed[t]);
+            D += res->w[t];
+        }
+        res->total = D;
+        res->stats.rounds = rounds;
+        res->stats.advances = slot_adv[s];
+        res->stats.pairs = m;
+        res->stats.tree_edges = m_out;
+        qq.result = std::move(res);
+    }
+    const auto t_end = std::chrono::steady_clock::now();
+    const double ms_total = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+    for (uint32_t s = 0; s < Q; s++) {
+        Query &qq = qs[act[s]];
+        if (!qq.result) continue;
+        steiner_stats &x = qq.result->stats;
+        x.ms_init = tm.ms(0, 1);
+        x.ms_voronoi = tm.ms(1, 2);
+        x.ms_scan = tm.ms(2, 3);
+        x.ms_compact = tm.ms(3, 4);
+        x.ms_mst = ms_mst;
+        x.ms_expand = ms_expand;
+        x.ms_total = ms_total;
+    }
+    return STEINER_OK;
+}
+
+}  // namespace stn

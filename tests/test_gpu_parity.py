@@ -1,0 +1,199 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+All arithmetic is integer, so every comparison is exact: Voronoi keys
+(dist << 32 | seed index), canonical predecessors, the entries of G'1, the
+tree's edge list, D, and the status code.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2205_14503_amd as st
+import pins
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+OPTION_SETS = {
+    "default": None,
+    "host": dict(driver=1),
+    "persistent": dict(driver=2),
+    "delta1": dict(delta=1),
+    "unbounded": dict(delta=0xFFFFFFFF),
+    "chunky": dict(small_max=1, chunk=64),
+    "persist_odd": dict(driver=2, small_max=2, chunk=64, delta=3, block=1024),
+}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def stream():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    torch.cuda.set_device(0)
+    st.load()
+    return torch.cuda.current_stream()
+
+
+def gpu_code(fn, *a, **kw):
+    try:
+        return st.OK, fn(*a, **kw)
+    except st.SteinerError as e:
+        return e.code, None
+
+
+def check_case(g, seeds, stream, options, what=""):
+    ref = O.solve(g, seeds)
+    _, S = O.canon_seeds(g.n, seeds)
+    with st.Graph(g, 0, stream) as dg:
+        code, tree = gpu_code(dg.solve, seeds, options)
+        assert code == ref.code, f"{what}: status {code} vs oracle {ref.code}"
+        if code == st.OK:
+            assert tree.edges == ref.edges, f"{what}: tree differs"
+            assert tree.total == ref.total
+        if len(S) >= 2:
+            dist, src = O.voronoi(g, S)
+            ovf = O.check_dist(dist)
+            code, kp = gpu_code(dg.voronoi, seeds, options)
+            rc_b, pi, pj, pb, pe = O.boundary(g, dist, src, len(S)) if ovf == O.OK else (ovf, None, None, None, None)
+            if ovf != O.OK or rc_b != O.OK:
+                assert code == st.EOVERFLOW, f"{what}: voronoi status {code}"
+            else:
+                assert code == st.OK
+                key, pred = kp
+                assert np.array_equal(key, O.packed_key(dist, src)), f"{what}: keys differ"
+                assert np.array_equal(pred, O.pred(g, S, dist, src)), f"{what}: pred differs"
+                gi, gj, gk = dg.boundary(seeds, options)
+                assert np.array_equal(gi, pi) and np.array_equal(gj, pj), f"{what}: G'1 pairs differ"
+                assert np.array_equal(gk, (pb << np.uint64(32)) | pe.astype(np.uint64)), f"{what}: G'1 values differ"
+
+
+def test_tiny_graphs_all_options(stream):
+    cases = list(pins.tiny_cases(seed=21, count=90))
+    for name, opt in OPTION_SETS.items():
+        say(f"tiny graphs, options={name}")
+        for t, (g, seeds) in enumerate(cases):
+            check_case(g, seeds, stream, opt, f"case {t} {name}")
+
+
+def test_error_codes_and_edge_cases(stream):
+    say("error codes")
+    big = 1 << 31
+    cases = [
+        (W.from_edges(4, [(0, 1, big), (1, 2, big), (0, 3, 1)]), [0, 3]),   # distance overflow
+        (W.from_edges(3, [(0, 1, big), (1, 2, big)]), [0, 2]),              # cross-cell sum overflow
+        (W.from_edges(3, [(0, 1, big - 1), (1, 2, big)]), [0, 2]),          # largest sum that fits
+        (W.from_edges(2, [(0, 1, 0xFFFFFFFE)]), [0, 1]),
+        (W.from_edges(5, [(0, 1, 3), (2, 3, 1), (3, 4, 2)]), [0, 4]),       # disconnected
+        (W.from_edges(5, [(0, 1, 3), (2, 3, 1), (3, 4, 2)]), [2, 4, 4]),
+        (W.from_edges(4, [(0, 1, 1), (1, 2, 1), (2, 3, 1)]), [2, 2, 2]),    # k = 1 after dedup
+        (W.from_edges(6, []), [1, 4]),                                       # no edges at all
+        (W.from_edges(4, [(0, 0, 5), (0, 1, 2), (0, 1, 1), (1, 1, 1), (1, 2, 7), (2, 3, 1), (2, 3, 1)]), [0, 3]),
+    ]
+    for t, (g, s) in enumerate(cases):
+        for name in ("default", "persistent"):
+            check_case(g, np.array(s, dtype=np.uint32), stream, OPTION_SETS[name], f"edge case {t} {name}")
+    g = W.from_edges(4, [(0, 1, 1), (1, 2, 1), (2, 3, 1)])
+    with st.Graph(g, 0, stream) as dg:
+        assert gpu_code(dg.solve, np.array([], dtype=np.uint32))[0] == st.EINVAL
+        assert gpu_code(dg.solve, [0, 4])[0] == st.EINVAL
+
+
+def test_upload_validation(stream):
+    say("upload validation")
+    good = W.from_edges(3, [(0, 1, 1), (1, 2, 2)])
+
+    def upload(rp, col, w, flags=0):
+        try:
+            h = st.steiner_graph_upload(3, rp, col, w, 0, stream, flags)
+            st.steiner_graph_free(h)
+            return st.OK
+        except st.SteinerError as e:
+            return e.code
+
+    assert upload(good.row_ptr, good.col, good.w, flags=1) == st.OK
+    w0 = good.w.copy(); w0[0] = 0
+    assert upload(good.row_ptr, good.col, w0) == st.EINVAL
+    c3 = good.col.copy(); c3[0] = 3
+    assert upload(good.row_ptr, c3, good.w) == st.EINVAL
+    uns = W.from_edges(3, [(1, 0, 1), (1, 2, 2)])
+    cu = uns.col.copy(); cu[[1, 2]] = cu[[2, 1]]
+    assert upload(uns.row_ptr, cu, uns.w) == st.EINVAL
+    rp = good.row_ptr.copy(); rp[1] = 5
+    assert upload(rp, good.col, good.w) == st.EINVAL
+    asym = good.w.copy(); asym[0] = 9
+    assert upload(good.row_ptr, good.col, asym, flags=1) == st.EINVAL
+    assert upload(good.row_ptr, good.col, asym, flags=0) == st.OK
+
+
+def test_er16k_config(stream):
+    g = W.make_graph("er16k")
+    seeds = W.make_seeds(g, 16)
+    for name in ("default", "host", "persistent", "delta1", "unbounded", "chunky"):
+        say(f"er16k options={name}")
+        check_case(g, seeds, stream, OPTION_SETS[name], f"er16k {name}")
+
+
+def test_rmat_hubs(stream):
+    g = W.rmat(16, 16, wlo=1, whi=1000)
+    cand = W.lcc(g)
+    for k in (2, 37, 1000):
+        seeds = W.sample(cand, k, master=3)
+        for name in ("default", "persistent", "chunky"):
+            say(f"rmat16 k={k} options={name}")
+            check_case(g, seeds, stream, OPTION_SETS[name], f"rmat16 k={k} {name}")
+
+
+def test_weight_one_ties(stream):
+    g = W.rmat(13, 8, wlo=1, whi=1)
+    seeds = W.sample(W.lcc(g), 300, master=5)
+    for name in ("default", "persistent", "unbounded"):
+        say(f"rmat13 unit weights options={name}")
+        check_case(g, seeds, stream, OPTION_SETS[name], f"unit {name}")
+    gg = W.grid(61, 67, 1, 2)
+    seeds = W.sample(np.arange(gg.n, dtype=np.uint32), 150, master=6)
+    for name in ("default", "persistent"):
+        say(f"grid 61x67 w in [1,2] options={name}")
+        check_case(gg, seeds, stream, OPTION_SETS[name], f"grid12 {name}")
+
+
+def test_grid2048_full_size(stream):
+    g = W.make_graph("grid2048")
+    seeds = W.make_seeds(g, 100)
+    say("grid2048 oracle")
+    ref = O.solve(g, seeds)
+    assert ref.code == O.OK
+    want_key = O.packed_key(ref.dist, ref.src)
+    with st.Graph(g, 0, stream) as dg:
+        for name in ("default", "persistent"):
+            say(f"grid2048 options={name}")
+            tree = dg.solve(seeds, OPTION_SETS[name])
+            assert tree.edges == ref.edges and tree.total == ref.total
+            key, pred = dg.voronoi(seeds, OPTION_SETS[name])
+            assert np.array_equal(key, want_key)
+            assert np.array_equal(pred, ref.pred)
+
+
+def test_batch_equals_single_and_oracle(stream):
+    g = W.rmat(14, 16, wlo=1, whi=1000)
+    cand = W.lcc(g)
+    sets = [W.sample(cand, int(k), master=1, stream=200 + q) for q, k in enumerate([3, 17, 2, 64, 9, 250, 5, 1])]
+    sets.append(np.array([int(cand[0])] * 3, dtype=np.uint32))  # k = 1 after dedup
+    with st.Graph(g, 0, stream) as dg:
+        for name in ("default", "persistent"):
+            say(f"batch options={name}")
+            res = dg.solve_batch(sets, OPTION_SETS[name])
+            for q, (code, tree) in enumerate(res):
+                ref = O.solve(g, sets[q])
+                assert code == ref.code
+                if code == st.OK:
+                    assert tree.edges == ref.edges and tree.total == ref.total, f"query {q}"
+                    single = dg.solve(sets[q], OPTION_SETS[name])
+                    assert single.edges == tree.edges
