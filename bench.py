@@ -1,0 +1,171 @@
+"""Benchmark of the Steiner-tree hot path on one MI355X.
+
+One step = one complete steiner_solve (Alg. 2 Steps 1-7: seed set-up, Voronoi
+relaxation, pred + boundary scan, G'1 compaction, MST, pruning and
+expansion, sorted edge list and D) on a graph already resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  value = GTEPS of the whole step: undirected edges of
+the seeds' components divided by the mean step time.  The roofline object is
+for the dominant kernel (the relaxation kernel), from HIP events around each
+of its launches on the graph's stream; `traffic` comes from the committed
+rocprofv3 counter summary when it matches the current kernel source.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GTEPS + Steiner queries/s at 1 GPU (bit-exact vs oracle); p50/p99 query latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2205_14503_amd", "csrc", "kernels.hip")
+
+
+def algorithmic_bytes(n: int, nnz_reached: int, nnz: int):
+    """Bytes a work-efficient pass must move (layout: u32 row offsets, 8-byte
+    (col, w) entries, 8-byte keys, 4-byte pred)."""
+    b_vor = 8 * nnz_reached + 4 * (n + 1) + 16 * n
+    b_scan = 8 * nnz + 4 * (n + 1) + 20 * n
+    return b_vor, b_scan
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="grid2048")
+    ap.add_argument("--driver", type=int, default=0)
+    ap.add_argument("--delta", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2205_14503_amd as st
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    spec = W.WORKLOADS[args.workload]
+    t0 = time.time()
+    g = W.make_graph(args.workload)
+    k = spec["k"]
+    seeds = W.make_seeds(g, k)
+    labels = W.components(g)
+    comp = np.isin(labels, np.unique(labels[seeds]))
+    nnz_reached = int(g.degrees()[comp].sum())
+    print(f"[bench] {args.workload}: n={g.n} nnz={g.nnz} k={k} reached_nnz={nnz_reached} "
+          f"(generated in {time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+
+    opts = {"flags": st.FLAG_TIMING}
+    if args.driver:
+        opts["driver"] = args.driver
+    if args.delta:
+        opts["delta"] = args.delta
+    dg = st.Graph(g, 0, stream)
+    for _ in range(args.warmup):
+        tree = dg.solve(seeds, opts)
+    torch.cuda.synchronize()
+    lat, relax_ms, relax_launches, scan_ms, voronoi_ms, rounds = [], [], [], [], [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        tree = dg.solve(seeds, opts)
+        lat.append((time.perf_counter() - s0) * 1e3)
+        relax_ms.append(tree.stats["ms_relax_kernels"])
+        relax_launches.append(tree.stats["relax_launches"])
+        scan_ms.append(tree.stats["ms_scan"])
+        voronoi_ms.append(tree.stats["ms_voronoi"])
+        rounds.append(tree.stats["rounds"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    gteps = (nnz_reached / 2) / (ms_per_step * 1e-3) / 1e9
+
+    b_vor, b_scan = algorithmic_bytes(g.n, nnz_reached, g.nnz)
+    mean_relax = float(np.mean(relax_ms))
+    mean_launch = float(np.mean(relax_launches))
+    mean_scan = float(np.mean(scan_ms))
+    if mean_relax >= mean_scan:
+        kname, kbytes, kms, kl = "k_round (relaxation)", b_vor, mean_relax, mean_launch
+    else:
+        kname, kbytes, kms, kl = "k_scan (pred + boundary)", b_scan, mean_scan, 1.0
+    achieved = (kbytes / kl) / (kms / kl * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            tf = json.load(open(TRAFFIC_FILE))
+            ent = tf.get(args.workload)
+            if ent and ent.get("kernel_sha") == kernel_sha():
+                traffic = ent["bytes_per_launch"]
+        except Exception:
+            traffic = None
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "algorithmic_bytes_per_step": kbytes, "launches_per_step": kl,
+                "avg_launch_us": round(kms / kl * 1e3, 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        times = []
+        c0 = time.perf_counter()
+        while not times or (time.perf_counter() - c0) < args.cpu_seconds:
+            s0 = time.perf_counter()
+            ref = oracle.solve(g, seeds)
+            times.append(time.perf_counter() - s0)
+        assert ref.code == oracle.OK and ref.edges == tree.edges and ref.total == tree.total, \
+            "GPU tree differs from the oracle"
+        cpu_gteps = (nnz_reached / 2) / float(np.mean(times)) / 1e9
+        cpu = {"value": round(cpu_gteps, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": f"{len(times)} full oracle solves of the same workload (single thread), "
+                         f"mean {np.mean(times):.2f} s",
+               "queries_per_s": round(1.0 / float(np.mean(times)), 4)}
+
+    line = {
+        "metric": METRIC,
+        "value": round(gteps, 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "k": k, "seed": 1,
+                   "weights": [spec["wlo"], spec["whi"]], "reached_nnz": nnz_reached},
+        "queries_per_s": round(1e3 / ms_per_step, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 4),
+        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+        "phases_ms": {"voronoi": round(float(np.mean(voronoi_ms)), 4), "relax_kernels": round(mean_relax, 4),
+                      "scan": round(mean_scan, 4), "rounds": float(np.mean(rounds))},
+        "tree": {"edges": len(tree.a), "D": tree.total},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

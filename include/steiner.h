@@ -70,7 +70,8 @@ typedef struct steiner_options {
     uint32_t small_max;   /* rows up to this degree are expanded wave-cooperatively; 0 = default */
     uint32_t chunk;       /* larger rows are split into chunks of this many edges; 0 = default */
     uint32_t flags;       /* STEINER_FLAG_* */
-    uint32_t reserved;
+    uint32_t local_iters; /* batches of 64 improved vertices a wave expands itself before deferring the rest
+                             to the next round; 0 = default, 0xFFFFFFFF = none */
 } steiner_options;
 
 #define STEINER_FLAG_TIMING 1u /* record per-phase device times (adds synchronisation) */
@@ -81,7 +82,13 @@ typedef struct steiner_stats {
     uint32_t advances;        /* bucket advances (summed over queries) */
     uint32_t pairs;           /* entries of G'1 (cell pairs joined by a cross-cell edge) */
     uint32_t tree_edges;      /* |E_S| */
-    double ms_init, ms_voronoi, ms_scan, ms_compact, ms_mst, ms_expand, ms_total; /* device/host phase times */
+    uint32_t relax_launches;  /* kernel launches of the relaxation pass */
+    uint32_t reserved;
+    /* Phase times in ms.  With STEINER_FLAG_TIMING the device phases come from
+     * HIP events on the graph's stream and ms_relax_kernels is the summed
+     * duration of the relaxation kernels alone (event pair per launch);
+     * otherwise only ms_total (host wall clock) is set. */
+    double ms_init, ms_voronoi, ms_scan, ms_compact, ms_mst, ms_expand, ms_total, ms_relax_kernels;
 } steiner_stats;
 
 /* Upload a graph from HOST arrays (copied; the caller keeps ownership).

@@ -47,14 +47,14 @@ class SteinerError(RuntimeError):
 
 class steiner_options(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint32) for name in
-                ("delta", "driver", "block", "grid", "small_max", "chunk", "flags", "reserved")]
+                ("delta", "driver", "block", "grid", "small_max", "chunk", "flags", "local_iters")]
 
 
 class steiner_stats(ctypes.Structure):
-    _fields_ = [("rounds", ctypes.c_uint32), ("advances", ctypes.c_uint32), ("pairs", ctypes.c_uint32),
-                ("tree_edges", ctypes.c_uint32)] + [
+    _fields_ = [(name, ctypes.c_uint32) for name in
+                ("rounds", "advances", "pairs", "tree_edges", "relax_launches", "reserved")] + [
         (name, ctypes.c_double) for name in
-        ("ms_init", "ms_voronoi", "ms_scan", "ms_compact", "ms_mst", "ms_expand", "ms_total")]
+        ("ms_init", "ms_voronoi", "ms_scan", "ms_compact", "ms_mst", "ms_expand", "ms_total", "ms_relax_kernels")]
 
 
 _lib = None

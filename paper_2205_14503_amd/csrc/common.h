@@ -52,7 +52,8 @@ struct Counters {
     uint32_t bar_count;  // persistent-kernel grid barrier
     uint32_t bar_gen;
     uint32_t abort;      // set when a barrier wait gives up
-    uint32_t pad[7];
+    uint32_t blocks_done; // workgroups finished in the current round (last one decides)
+    uint32_t pad[6];
 };
 
 struct DevGraph {
@@ -89,6 +90,7 @@ struct VorParams {
     uint32_t delta;
     uint32_t small_max;
     uint32_t chunk;
+    uint32_t local_iters; // batches of the wave-local queue expanded per unit (0 = no local queue)
 };
 
 enum : uint32_t {

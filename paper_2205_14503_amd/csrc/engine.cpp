@@ -118,8 +118,10 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
     r.grid = 0;
     r.small_max = 64;
     r.chunk = 512;
+    r.local_iters = 8;
     r.timing = false;
     if (const char *s = getenv("STEINER_DRIVER")) r.driver = (uint32_t)atoi(s);
+    if (const char *s = getenv("STEINER_LOCAL")) r.local_iters = (uint32_t)strtoul(s, nullptr, 10);
     if (const char *s = getenv("STEINER_DELTA")) r.delta = (uint32_t)strtoul(s, nullptr, 10);
     if (o) {
         if (o->delta) r.delta = o->delta;
@@ -128,12 +130,14 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
         if (o->grid) r.grid = o->grid;
         if (o->small_max) r.small_max = o->small_max;
         if (o->chunk) r.chunk = o->chunk;
+        if (o->local_iters) r.local_iters = o->local_iters == 0xFFFFFFFFu ? 0 : o->local_iters;
         r.timing = (o->flags & STEINER_FLAG_TIMING) != 0;
     }
     if (r.delta == 0) r.delta = 1;
     if (r.block < 64 || r.block > 1024 || r.block % 64) r.block = 256;
+    if (r.driver == 2 && r.block > 512) r.block = 512;  // LDS of the persistent kernel
     if (r.chunk < 64) r.chunk = 64;
-    if (r.grid == 0) r.grid = (uint32_t)std::max(1, g->cu_count) * (r.driver == 2 ? 2u : 4u) * (1024u / r.block);
+    if (r.grid == 0) r.grid = (uint32_t)std::max(1, g->cu_count) * 2u * (r.driver == 2 ? 1024u / r.block : 1u);
     return r;
 }
 

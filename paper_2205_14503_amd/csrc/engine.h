@@ -36,7 +36,7 @@ struct HostPinned {
 };
 
 struct Options {
-    uint32_t delta, driver, block, grid, small_max, chunk;
+    uint32_t delta, driver, block, grid, small_max, chunk, local_iters;
     bool timing;
 };
 

@@ -24,7 +24,6 @@ namespace stn {
 
 #define DEVI __device__ __forceinline__
 
-constexpr uint32_t MAX_WAVES = 16;  // 1024-thread workgroups
 constexpr uint32_t PERSIST_SLOTS = 256;
 
 DEVI uint32_t lane() { return __lane_id(); }
@@ -111,10 +110,28 @@ DEVI void append_b(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, 
     }
 }
 
+// Per-wave LDS queue of improved small-degree vertices that the wave expands
+// itself within the same round, so one round advances many hops along
+// long shortest paths (high-diameter graphs otherwise need a global round per
+// hop).  Anything the queue cannot hold goes to the next round's list.
+constexpr uint32_t LQ_CAP = 256;
+
+struct WaveScratch {
+    uint32_t incl[64];
+    uint32_t beg[64];
+    uint32_t slot[64];
+    uint32_t pad[64];
+    uint64_t key[64];
+    uint64_t lq[LQ_CAP];
+};
+
 // Relax one edge (src key ksrc, target u, weight w) of query `slot` and
-// schedule u if its key improved.  Must be reached by every lane of the wave.
+// schedule u if its key improved: into the wave's local queue (lq != null,
+// small row, room left), else into the next round's list once per round
+// (stamp), or park it if its distance is beyond the query's bucket.  Must be
+// reached by every lane of the wave.
 DEVI void relax_push(const VorParams &P, const RoundIdx &R, const uint64_t *thr, bool valid, uint32_t slot,
-                     uint64_t ksrc, uint32_t u, uint32_t w) {
+                     uint64_t ksrc, uint32_t u, uint32_t w, uint64_t *lq, uint32_t &lq_head, uint32_t &lq_tail) {
     const uint32_t n = P.g.n;
     bool improved = false;
     uint32_t nd = 0;
@@ -132,17 +149,12 @@ DEVI void relax_push(const VorParams &P, const RoundIdx &R, const uint64_t *thr,
             }
         }
     }
-    bool claim = false, park = false;
+    bool near = false, park = false;
     uint32_t deg = 0;
     if (improved) {
         if ((uint64_t)nd < thr[slot]) {
-            uint32_t *sp = P.aux + (size_t)slot * n + u;
-            if (atomicExch(sp, R.r + 1) != R.r + 1) {
-                claim = true;
-                deg = P.g.rp[u + 1] - P.g.rp[u];
-                uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + slot;
-                if (*nm == 0) *nm = 1;
-            }
+            near = true;
+            deg = P.g.rp[u + 1] - P.g.rp[u];
         } else {
             park = true;
         }
@@ -152,29 +164,40 @@ DEVI void relax_push(const VorParams &P, const RoundIdx &R, const uint64_t *thr,
         uint32_t *fm = P.far_min + (size_t)R.b * P.nslots + slot;
         if (nd < *fm) atomicMin(fm, nd);
     }
+    bool local = false;
+    if (lq) {
+        const bool want = near && deg <= P.small_max;
+        const uint64_t m = __ballot(want);
+        if (m) {
+            const uint32_t space = LQ_CAP - (lq_tail - lq_head);
+            const uint32_t rank = lanes_below(m);
+            local = want && rank < space;
+            if (local) lq[(lq_tail + rank) % LQ_CAP] = s_item(slot, u);
+            lq_tail += min((uint32_t)__popcll(m), space);
+        }
+    }
+    bool claim = false;
+    if (near && !local) {
+        uint32_t *sp = P.aux + (size_t)slot * n + u;
+        if (atomicExch(sp, R.r + 1) != R.r + 1) {
+            claim = true;
+            uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + slot;
+            if (*nm == 0) *nm = 1;
+        }
+    }
     append_s(P, R.nxt, R.c_nxt, claim && deg <= P.small_max, s_item(slot, u));
     append_b(P, R.nxt, R.c_nxt, claim && deg > P.small_max, slot, u, deg);
 }
 
-struct WaveScratch {
-    uint32_t incl[64];
-    uint32_t beg[64];
-    uint32_t aux[64];
-    uint32_t flag[64];
-    uint64_t key[64];
-};
-
-// One wave expands 64 frontier items of small degree.
-DEVI void process_s_group(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t gidx,
-                          uint32_t cnt, WaveScratch *L) {
+// Expands one frontier item per lane (lanes with `has`): all edges of the
+// items' rows, 64 edges per step, balanced across the wave by a prefix sum of
+// the degrees (coalesced 8-byte (col, w) loads within each row).
+DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *thr, bool has, uint32_t slot,
+                       uint32_t v, WaveScratch *L, bool use_lq, uint32_t &lq_head, uint32_t &lq_tail) {
     const uint32_t ln = lane();
-    const uint32_t idx = gidx * 64 + ln;
-    uint32_t slot = 0, beg = 0, deg = 0;
+    uint32_t beg = 0, deg = 0;
     uint64_t kv = KEY_INF;
-    if (idx < cnt) {
-        uint64_t it = P.items_s[R.cur][idx];
-        slot = (uint32_t)(it >> 32);
-        uint32_t v = (uint32_t)it;
+    if (has) {
         kv = ld_agent(P.key + (size_t)slot * P.g.n + v);
         beg = P.g.rp[v];
         deg = P.g.rp[v + 1] - beg;
@@ -182,11 +205,13 @@ DEVI void process_s_group(const VorParams &P, const RoundIdx &R, const uint64_t 
     }
     const uint32_t incl = wave_incl_scan(deg);
     const uint32_t total = __shfl(incl, 63, 64);
+    wave_sync();
     L->incl[ln] = incl;
     L->beg[ln] = beg;
-    L->aux[ln] = slot;
+    L->slot[ln] = slot;
     L->key[ln] = kv;
     wave_sync();
+    uint64_t *lq = use_lq ? L->lq : nullptr;
     for (uint32_t base = 0; base < total; base += 64) {
         const uint32_t t = base + ln;
         const bool valid = t < total;
@@ -202,13 +227,13 @@ DEVI void process_s_group(const VorParams &P, const RoundIdx &R, const uint64_t 
         const uint32_t ex = j ? L->incl[j - 1] : 0;
         uint2 a = make_uint2(0, 0);
         if (valid) a = P.g.adj[L->beg[j] + (t - ex)];
-        relax_push(P, R, thr, valid, L->aux[j], L->key[j], a.x, a.y);
+        relax_push(P, R, thr, valid, L->slot[j], L->key[j], a.x, a.y, lq, lq_head, lq_tail);
     }
-    wave_sync();
 }
 
 // One wave expands one chunk of a large row.
-DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t idx) {
+DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t idx, WaveScratch *L,
+                          bool use_lq, uint32_t &lq_head, uint32_t &lq_tail) {
     const uint64_t it = P.items_b[R.cur][idx];
     const uint32_t slot = (uint32_t)(it >> 52);
     const uint32_t c = (uint32_t)(it >> 32) & 0xFFFFFu;
@@ -218,12 +243,44 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
     const uint32_t lim = P.g.rp[v + 1];
     uint32_t end = (lim - beg > P.chunk) ? beg + P.chunk : lim;
     if (kv == KEY_INF) end = beg;
+    uint64_t *lq = use_lq ? L->lq : nullptr;
     for (uint32_t e0 = beg; e0 < end; e0 += 64) {
         const uint32_t e = e0 + lane();
         const bool valid = e < end;
         uint2 a = make_uint2(0, 0);
         if (valid) a = P.g.adj[e];
-        relax_push(P, R, thr, valid, slot, kv, a.x, a.y);
+        relax_push(P, R, thr, valid, slot, kv, a.x, a.y, lq, lq_head, lq_tail);
+    }
+}
+
+// Expand the wave's local queue for at most `budget` batches of 64, then move
+// what is left to the next round's list (once per vertex per round).
+DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr, WaveScratch *L, uint32_t budget,
+                      uint32_t &h, uint32_t &t) {
+    for (uint32_t it = 0; it < budget && h != t; it++) {
+        const uint32_t take = min(t - h, 64u);
+        wave_sync();
+        const bool has = lane() < take;
+        const uint64_t item = has ? L->lq[(h + lane()) % LQ_CAP] : 0;
+        h += take;
+        expand_items(P, R, thr, has, (uint32_t)(item >> 32), (uint32_t)item, L, true, h, t);
+    }
+    while (h != t) {
+        const uint32_t take = min(t - h, 64u);
+        wave_sync();
+        const bool has = lane() < take;
+        const uint64_t item = has ? L->lq[(h + lane()) % LQ_CAP] : 0;
+        h += take;
+        bool claim = false;
+        if (has) {
+            const uint32_t slot = (uint32_t)(item >> 32), v = (uint32_t)item;
+            if (atomicExch(P.aux + (size_t)slot * P.g.n + v, R.r + 1) != R.r + 1) {
+                claim = true;
+                uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + slot;
+                if (*nm == 0) *nm = 1;
+            }
+        }
+        append_s(P, R.nxt, R.c_nxt, claim, item);
     }
 }
 
@@ -231,11 +288,18 @@ DEVI void relax_round_body(const VorParams &P, const RoundIdx &R, const uint64_t
                            WaveScratch *L, uint32_t wave_gid, uint32_t nwaves) {
     const uint32_t ng = (cs + 63) / 64;
     const uint32_t units = ng + cb;
+    const bool use_lq = P.local_iters != 0;
     for (uint32_t u = wave_gid; u < units; u += nwaves) {
-        if (u < ng)
-            process_s_group(P, R, thr, u, cs, L);
-        else
-            process_b_chunk(P, R, thr, u - ng);
+        uint32_t h = 0, t = 0;
+        if (u < ng) {
+            const uint32_t idx = u * 64 + lane();
+            const bool has = idx < cs;
+            const uint64_t it = has ? P.items_s[R.cur][idx] : 0;
+            expand_items(P, R, thr, has, (uint32_t)(it >> 32), (uint32_t)it, L, use_lq, h, t);
+        } else {
+            process_b_chunk(P, R, thr, u - ng, L, use_lq, h, t);
+        }
+        if (use_lq) drain_local(P, R, thr, L, P.local_iters, h, t);
     }
 }
 
@@ -269,16 +333,18 @@ DEVI void decide_slot(const VorParams &P, uint32_t r, uint32_t q, uint64_t *thr,
 }
 
 // Parked vertices of every advancing query whose distance falls below the new
-// bucket end join the next round's frontier; stale marks are cleared; the
-// minimum parked distance left over feeds the next decision.
-DEVI void advance_body(const VorParams &P, uint32_t r, const uint64_t *thr, const uint64_t *thr_prev,
-                       const uint32_t *adv, uint32_t wave_gid, uint32_t nwaves) {
+// bucket end join list `list` (stamp `stamp`); stale marks are cleared; the
+// minimum parked distance left over goes to far_min[fm_buf]; if nm_buf >= 0
+// the query's near mark in that buffer is set when something was pushed.
+DEVI void advance_body(const VorParams &P, const uint64_t *thr, const uint64_t *thr_prev, const uint32_t *adv,
+                       uint32_t stamp, uint32_t list, uint32_t cidx, uint32_t fm_buf, int nm_buf, uint32_t wave_gid,
+                       uint32_t nwaves) {
     const uint32_t n = P.g.n;
-    const RoundIdx R = round_idx(r);
     for (uint32_t q = 0; q < P.nslots; q++) {
         if (!adv[q]) continue;
         const uint64_t lo = thr_prev[q], hi = thr[q];
         uint32_t kept = DIST_INF;
+        bool pushed = false;
         for (uint32_t base = wave_gid * 64; base < n; base += nwaves * 64) {
             const uint32_t v = base + lane();
             bool push = false;
@@ -291,7 +357,7 @@ DEVI void advance_body(const VorParams &P, uint32_t r, const uint64_t *thr, cons
                         P.dirty[o] = 0;
                     } else if (d < hi) {
                         P.dirty[o] = 0;
-                        P.aux[o] = r + 1;
+                        P.aux[o] = stamp;
                         deg = P.g.rp[v + 1] - P.g.rp[v];
                         push = true;
                     } else {
@@ -299,30 +365,46 @@ DEVI void advance_body(const VorParams &P, uint32_t r, const uint64_t *thr, cons
                     }
                 }
             }
-            append_s(P, R.nxt, R.c_nxt, push && deg <= P.small_max, s_item(q, v));
-            append_b(P, R.nxt, R.c_nxt, push && deg > P.small_max, q, v, deg);
+            pushed |= __ballot(push) != 0;
+            append_s(P, list, cidx, push && deg <= P.small_max, s_item(q, v));
+            append_b(P, list, cidx, push && deg > P.small_max, q, v, deg);
         }
         kept = wave_min(kept);
-        if (lane() == 0 && kept != DIST_INF) atomicMin(P.far_min + (size_t)((r + 1) % 3u) * P.nslots + q, kept);
+        if (lane() == 0) {
+            if (kept != DIST_INF) atomicMin(P.far_min + (size_t)fm_buf * P.nslots + q, kept);
+            if (pushed && nm_buf >= 0) P.near_mark[(size_t)nm_buf * P.nslots + q] = 1;
+        }
     }
 }
 
 // ------------------------------------------------------------ host-stepped
 
-__global__ void __launch_bounds__(1024) k_relax(VorParams P) {
-    __shared__ WaveScratch s_wave[MAX_WAVES];
+// One round per launch: the advance scan decided at the end of the previous
+// round (its pushes are processed one round later), the relaxation of this
+// round's list, and, in the last workgroup to finish, the bucket decision.
+__global__ void __launch_bounds__(1024) k_round(VorParams P) {
+    extern __shared__ __align__(16) unsigned char dyn_smem[];
+    WaveScratch *s_wave = (WaveScratch *)dyn_smem;
+    __shared__ int s_last, s_adv, s_act;
     if (ld_agent(&P.pass->all_done)) return;
     const uint32_t r = ld_agent(&P.pass->round);
     const RoundIdx R = round_idx(r);
-    const uint32_t cs = min(ld_agent(&P.cnt->s[r % 3u]), P.cap_s), cb = min(ld_agent(&P.cnt->b[r % 3u]), P.cap_b);
     const uint32_t wpb = blockDim.x / 64, w = threadIdx.x / 64;
-    relax_round_body(P, R, P.slot.thr, cs, cb, &s_wave[w], blockIdx.x * wpb + w, gridDim.x * wpb);
-}
+    const uint32_t wave_gid = blockIdx.x * wpb + w, nwaves = gridDim.x * wpb;
+    if (ld_agent(&P.pass->any_adv))
+        advance_body(P, P.slot.thr, P.slot.thr_prev, P.slot.adv, r + 1, R.nxt, R.c_nxt, R.b, (int)R.b, wave_gid,
+                     nwaves);
+    const uint32_t cs = min(ld_agent(&P.cnt->s[r % 3u]), P.cap_s), cb = min(ld_agent(&P.cnt->b[r % 3u]), P.cap_b);
+    relax_round_body(P, R, P.slot.thr, cs, cb, &s_wave[w], wave_gid, nwaves);
 
-__global__ void __launch_bounds__(256) k_control(VorParams P) {
-    __shared__ int s_adv, s_act;
-    if (P.pass->all_done) return;
-    const uint32_t r = P.pass->round;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(&P.cnt->blocks_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
     if (threadIdx.x == 0) { s_adv = 0; s_act = 0; }
     __syncthreads();
     bool aa = false, act = false;
@@ -339,17 +421,12 @@ __global__ void __launch_bounds__(256) k_control(VorParams P) {
     if (threadIdx.x == 0) {
         P.cnt->s[(r + 2) % 3u] = 0;
         P.cnt->b[(r + 2) % 3u] = 0;
+        P.cnt->blocks_done = 0;
         P.pass->any_adv = s_adv;
         if (!s_act) P.pass->all_done = 1;
         P.pass->round = r + 1;
+        __threadfence();
     }
-}
-
-__global__ void __launch_bounds__(1024) k_advance(VorParams P) {
-    if (!ld_agent(&P.pass->any_adv)) return;
-    const uint32_t r = ld_agent(&P.pass->round) - 1;
-    const uint32_t wpb = blockDim.x / 64, w = threadIdx.x / 64;
-    advance_body(P, r, P.slot.thr, P.slot.thr_prev, P.slot.adv, blockIdx.x * wpb + w, gridDim.x * wpb);
 }
 
 // ---------------------------------------------------------------- persistent
@@ -388,7 +465,8 @@ DEVI bool grid_barrier(Counters *cn, uint32_t nblocks, PassCtl *pass, int *s_abo
 }
 
 __global__ void __launch_bounds__(1024) k_persistent(VorParams P, uint32_t max_rounds) {
-    __shared__ WaveScratch s_wave[MAX_WAVES];
+    extern __shared__ __align__(16) unsigned char dyn_smem[];
+    WaveScratch *s_wave = (WaveScratch *)dyn_smem;
     __shared__ uint64_t s_thr[PERSIST_SLOTS], s_thr_prev[PERSIST_SLOTS];
     __shared__ uint32_t s_carry[PERSIST_SLOTS], s_active[PERSIST_SLOTS], s_adv[PERSIST_SLOTS];
     __shared__ uint32_t s_done[PERSIST_SLOTS], s_advances[PERSIST_SLOTS];
@@ -436,7 +514,8 @@ __global__ void __launch_bounds__(1024) k_persistent(VorParams P, uint32_t max_r
         __syncthreads();
         const bool any_adv = s_any_adv != 0, any_act = s_any_act != 0;
         if (any_adv) {
-            advance_body(P, r, s_thr, s_thr_prev, s_adv, wave_gid, nwaves);
+            advance_body(P, s_thr, s_thr_prev, s_adv, r + 1, (r + 1) & 1u, (r + 1) % 3u, (r + 1) % 3u, -1, wave_gid,
+                         nwaves);
             if (!(ok = grid_barrier(P.cnt, gridDim.x, P.pass, &s_abort))) break;
         }
         r++;
@@ -482,6 +561,7 @@ __global__ void k_pass_reset(VorParams P) {
         P.cnt->bar_count = 0;
         P.cnt->bar_gen = 0;
         P.cnt->abort = 0;
+        P.cnt->blocks_done = 0;
     }
     for (uint32_t q = t; q < P.nslots; q += gridDim.x * blockDim.x) {
         for (int b = 0; b < 3; b++) {
@@ -836,10 +916,10 @@ hipError_t launch_slot_start(const VorParams &P, uint32_t slot, const uint32_t *
     return hipGetLastError();
 }
 
+static size_t wave_smem(uint32_t block) { return (size_t)(block / 64) * sizeof(WaveScratch); }
+
 hipError_t launch_round(const VorParams &P, uint32_t grid, uint32_t block, hipStream_t s) {
-    hipLaunchKernelGGL(k_relax, dim3(grid), dim3(block), 0, s, P);
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, s, P);
-    hipLaunchKernelGGL(k_advance, dim3(grid), dim3(block), 0, s, P);
+    hipLaunchKernelGGL(k_round, dim3(grid), dim3(block), wave_smem(block), s, P);
     return hipGetLastError();
 }
 
@@ -847,7 +927,8 @@ int persistent_max_grid(uint32_t block) {
     int dev = 0, per_cu = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent, (int)block, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent, (int)block, wave_smem(block)) != hipSuccess)
+        return 0;
     return per_cu * prop.multiProcessorCount;
 }
 
@@ -856,7 +937,7 @@ hipError_t launch_persistent(const VorParams &P, uint32_t grid, uint32_t block, 
     if (P.nslots > PERSIST_SLOTS) return hipErrorInvalidValue;
     VorParams p = P;
     void *args[] = {&p, &max_rounds};
-    return hipLaunchCooperativeKernel((const void *)k_persistent, dim3(grid), dim3(block), args, 0, s);
+    return hipLaunchCooperativeKernel((const void *)k_persistent, dim3(grid), dim3(block), args, wave_smem(block), s);
 }
 
 hipError_t launch_scan(const ScanParams &S, uint32_t grid, uint32_t block, hipStream_t s) {

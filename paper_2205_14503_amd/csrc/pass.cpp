@@ -153,6 +153,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     P.delta = o.delta;
     P.small_max = o.small_max;
     P.chunk = o.chunk;
+    P.local_iters = o.local_iters;
 
     // Per-slot pointer tables (host image, then one copy).
     {
@@ -204,6 +205,17 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
 
     // ------------------------------------------------- Step 1: Voronoi cells
     PassCtl *hpass = (PassCtl *)(hctl + L.pass);
+    // per-launch event pairs of the relaxation kernels (timing mode only)
+    std::vector<hipEvent_t> kev;
+    auto kmark = [&]() {
+        if (!o.timing) return;
+        hipEvent_t e;
+        if (hipEventCreate(&e) == hipSuccess) {
+            (void)hipEventRecord(e, st);
+            kev.push_back(e);
+        }
+    };
+    uint32_t relax_launches = 0;
     const uint32_t round_cap = 1u << 26;
     const uint32_t rounds_per_launch = 4096;
     const double wall_cap_s = 120.0;
@@ -219,8 +231,11 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     }
     if (persistent) {
         for (;;) {
-            if ((rc = hip_check(launch_persistent(P, pgrid, o.block, rounds_per_launch, st), "persistent pass")))
-                return rc;
+            kmark();
+            rc = hip_check(launch_persistent(P, pgrid, o.block, rounds_per_launch, st), "persistent pass");
+            kmark();
+            relax_launches++;
+            if (rc) return rc;
             if ((rc = hip_check(hipMemcpyAsync(hpass, P.pass, sizeof(PassCtl), hipMemcpyDeviceToHost, st), "D2H pass")))
                 return rc;
             if ((rc = hip_check(hipStreamSynchronize(st), "persistent sync"))) return rc;
@@ -233,8 +248,13 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     } else {
         uint32_t chunk_rounds = 4, launched = 0;
         for (;;) {
-            for (uint32_t i = 0; i < chunk_rounds; i++)
-                if ((rc = hip_check(launch_round(P, o.grid, o.block, st), "round"))) return rc;
+            for (uint32_t i = 0; i < chunk_rounds; i++) {
+                kmark();
+                rc = hip_check(launch_round(P, o.grid, o.block, st), "round");
+                kmark();
+                relax_launches++;
+                if (rc) return rc;
+            }
             launched += chunk_rounds;
             if ((rc = hip_check(hipMemcpyAsync(hpass, P.pass, sizeof(PassCtl), hipMemcpyDeviceToHost, st), "D2H pass")))
                 return rc;
@@ -247,6 +267,13 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         }
     }
     const uint32_t rounds = hpass->round;
+    double ms_relax = 0.0;
+    for (size_t i = 0; i + 1 < kev.size(); i += 2) {
+        float m = 0.f;
+        (void)hipEventSynchronize(kev[i + 1]);
+        if (hipEventElapsedTime(&m, kev[i], kev[i + 1]) == hipSuccess) ms_relax += m;
+    }
+    for (hipEvent_t e : kev) (void)hipEventDestroy(e);
     tm.mark();  // 2
 
     // ------------------------------ canonical pred + Step 2 boundary scan
@@ -396,6 +423,8 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         x.ms_mst = ms_mst;
         x.ms_expand = ms_expand;
         x.ms_total = ms_total;
+        x.ms_relax_kernels = ms_relax;
+        x.relax_launches = relax_launches;
     }
     return STEINER_OK;
 }
