@@ -49,6 +49,7 @@ def main():
     ap.add_argument("--driver", type=int, default=0)
     ap.add_argument("--delta", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -81,6 +82,12 @@ def main():
     if args.delta:
         opts["delta"] = args.delta
     dg = st.Graph(g, 0, stream)
+    tuned = None
+    if not args.no_tune and not args.delta:
+        t0 = time.time()
+        tuned = dg.tune(seeds)  # set-up, like the upload: picks delta and the local-queue depth
+        tuned = {"delta": tuned["delta"], "local_iters": tuned["local_iters"], "seconds": round(time.time() - t0, 2)}
+        print(f"[bench] tuned {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         tree = dg.solve(seeds, opts)
     torch.cuda.synchronize()
@@ -161,6 +168,7 @@ def main():
         "phases_ms": {"voronoi": round(float(np.mean(voronoi_ms)), 4), "relax_kernels": round(mean_relax, 4),
                       "scan": round(mean_scan, 4), "rounds": float(np.mean(rounds))},
         "tree": {"edges": len(tree.a), "D": tree.total},
+        "tuned": tuned,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -74,7 +74,9 @@ typedef struct steiner_options {
                              to the next round; 0 = default, 0xFFFFFFFF = none */
 } steiner_options;
 
-#define STEINER_FLAG_TIMING 1u /* record per-phase device times (adds synchronisation) */
+#define STEINER_FLAG_TIMING 1u   /* record per-phase device times (adds synchronisation) */
+#define STEINER_FLAG_COUNTERS 2u /* count relaxation events on the device (the analogue of the
+                                    paper's per-phase message counts, Fig. 6) */
 
 /* Per-solve statistics (filled for steiner_solve / steiner_solve_batch results). */
 typedef struct steiner_stats {
@@ -89,6 +91,12 @@ typedef struct steiner_stats {
      * duration of the relaxation kernels alone (event pair per launch);
      * otherwise only ms_total (host wall clock) is set. */
     double ms_init, ms_voronoi, ms_scan, ms_compact, ms_mst, ms_expand, ms_total, ms_relax_kernels;
+    /* With STEINER_FLAG_COUNTERS, summed over the pass (all queries of a
+     * batch): edges relaxed, atomicMins issued after the stale-value filter,
+     * keys improved, improved vertices expanded by the same wave, vertices
+     * moved to the next round's list, vertices parked beyond their bucket,
+     * frontier items expanded. */
+    uint64_t relax_attempts, relax_atomics, relax_improved, pushes_local, pushes_next, parked, items;
 } steiner_stats;
 
 /* Upload a graph from HOST arrays (copied; the caller keeps ownership).
@@ -106,6 +114,13 @@ int steiner_graph_upload_device(uint32_t n, uint64_t nnz, const void *d_row_ptr,
                                 steiner_graph **out);
 
 int steiner_graph_free(steiner_graph *g);
+
+/* Autotuner: times a small set of relaxation settings (bucket width, depth of
+ * the wave-local queue) on the given sample seed set and keeps the fastest as
+ * this graph's defaults for every later call that passes NULL options or zero
+ * fields.  Results never depend on the choice.  out (optional) receives the
+ * chosen settings.  EINVAL for fewer than 2 distinct seeds. */
+int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint32_t k, steiner_options *out);
 
 /* Alg. 2 end to end for one seed set (host array of k vertex ids). */
 int steiner_solve(steiner_graph *g, const uint32_t *seeds, uint32_t k, const steiner_options *opt,
@@ -149,6 +164,8 @@ int steiner_server_submit(steiner_server *s, const uint32_t *seeds, uint32_t k, 
 int steiner_server_wait(steiner_server *s, uint64_t ticket, int64_t timeout_us, steiner_result **out);
 /* Bytes a request with k seeds needs on the device (the admission charge). */
 uint64_t steiner_server_query_bytes(const steiner_server *s, uint32_t k);
+/* Stops the server; requests not yet finished are canceled.  No other call on
+ * this server may be in progress or follow. */
 int steiner_server_destroy(steiner_server *s);
 
 const char *steiner_strerror(int code);

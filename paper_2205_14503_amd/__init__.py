@@ -28,10 +28,11 @@ OK, EINVAL, ENOMEM, EDISCONNECTED, EOVERFLOW, EDEVICE, ETIMEDOUT, ECANCELED = 0,
 CODE_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDISCONNECTED: "EDISCONNECTED",
               EOVERFLOW: "EOVERFLOW", EDEVICE: "EDEVICE", ETIMEDOUT: "ETIMEDOUT", ECANCELED: "ECANCELED"}
 FLAG_TIMING = 1
+FLAG_COUNTERS = 2
 DRIVER_DEFAULT, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
 
 EXPORTS = [
-    "steiner_graph_upload", "steiner_graph_upload_device", "steiner_graph_free", "steiner_solve",
+    "steiner_graph_upload", "steiner_graph_upload_device", "steiner_graph_free", "steiner_graph_tune", "steiner_solve",
     "steiner_solve_batch", "steiner_result_edges", "steiner_result_total", "steiner_result_stats",
     "steiner_result_free", "steiner_voronoi", "steiner_boundary", "steiner_server_create",
     "steiner_server_submit", "steiner_server_wait", "steiner_server_query_bytes", "steiner_server_destroy",
@@ -54,7 +55,9 @@ class steiner_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint32) for name in
                 ("rounds", "advances", "pairs", "tree_edges", "relax_launches", "reserved")] + [
         (name, ctypes.c_double) for name in
-        ("ms_init", "ms_voronoi", "ms_scan", "ms_compact", "ms_mst", "ms_expand", "ms_total", "ms_relax_kernels")]
+        ("ms_init", "ms_voronoi", "ms_scan", "ms_compact", "ms_mst", "ms_expand", "ms_total", "ms_relax_kernels")] + [
+        (name, ctypes.c_uint64) for name in
+        ("relax_attempts", "relax_atomics", "relax_improved", "pushes_local", "pushes_next", "parked", "items")]
 
 
 _lib = None
@@ -74,6 +77,7 @@ def load(path: str | None = None):
         "steiner_graph_upload": (i32, [u32, u64, vp, vp, vp, i32, vp, u32, vp]),
         "steiner_graph_upload_device": (i32, [u32, u64, vp, vp, vp, i32, vp, u32, vp]),
         "steiner_graph_free": (i32, [vp]),
+        "steiner_graph_tune": (i32, [vp, vp, u32, vp]),
         "steiner_solve": (i32, [vp, vp, u32, vp, vp]),
         "steiner_solve_batch": (i32, [vp, u32, vp, vp, vp, vp, vp]),
         "steiner_result_edges": (i32, [vp, vp, vp, vp, vp]),
@@ -150,6 +154,14 @@ def steiner_graph_upload_device(n, row_ptr_t, col_t, w_t, device: int = 0, strea
 
 def steiner_graph_free(g: int) -> None:
     _check(load().steiner_graph_free(g))
+
+
+def steiner_graph_tune(g: int, seeds) -> dict:
+    """Pick the graph's default relaxation settings on a sample seed set."""
+    s = _u32(seeds)
+    o = steiner_options()
+    _check(load().steiner_graph_tune(g, s.ctypes.data if len(s) else None, len(s), ctypes.byref(o)))
+    return {name: getattr(o, name) for name, _ in steiner_options._fields_}
 
 
 @dataclass
@@ -303,6 +315,9 @@ class Graph:
 
     def solve(self, seeds, options=None) -> Tree:
         return steiner_solve(self.handle, seeds, options)
+
+    def tune(self, seeds) -> dict:
+        return steiner_graph_tune(self.handle, seeds)
 
     def solve_batch(self, seed_sets, options=None):
         return steiner_solve_batch(self.handle, seed_sets, options)

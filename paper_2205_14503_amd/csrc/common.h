@@ -54,7 +54,12 @@ struct Counters {
     uint32_t abort;      // set when a barrier wait gives up
     uint32_t blocks_done; // workgroups finished in the current round (last one decides)
     uint32_t pad[6];
+    // event counters (only with counting enabled): relaxation attempts,
+    // atomicMins issued, improvements, local-queue pushes, next-round pushes,
+    // parked vertices, items expanded
+    unsigned long long ev[8];
 };
+enum { EV_ATTEMPT = 0, EV_ATOMIC, EV_IMPROVED, EV_LOCAL, EV_GLOBAL, EV_PARK, EV_ITEMS, EV_N };
 
 struct DevGraph {
     uint32_t n;
@@ -91,6 +96,7 @@ struct VorParams {
     uint32_t small_max;
     uint32_t chunk;
     uint32_t local_iters; // batches of the wave-local queue expanded per unit (0 = no local queue)
+    uint32_t counting;    // 1: accumulate Counters::ev
 };
 
 enum : uint32_t {

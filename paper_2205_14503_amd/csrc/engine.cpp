@@ -112,14 +112,15 @@ int HostPinned::ensure(size_t want) {
 
 Options resolve_options(const steiner_graph *g, const steiner_options *o) {
     Options r;
-    r.delta = g->default_delta;
+    r.delta = g->tuned_delta ? g->tuned_delta : g->default_delta;
     r.driver = 1;
     r.block = 256;
     r.grid = 0;
     r.small_max = 64;
     r.chunk = 512;
-    r.local_iters = 8;
+    r.local_iters = g->tuned_local ? (g->tuned_local == 0xFFFFFFFFu ? 0 : g->tuned_local) : 8;
     r.timing = false;
+    r.counting = false;
     if (const char *s = getenv("STEINER_DRIVER")) r.driver = (uint32_t)atoi(s);
     if (const char *s = getenv("STEINER_LOCAL")) r.local_iters = (uint32_t)strtoul(s, nullptr, 10);
     if (const char *s = getenv("STEINER_DELTA")) r.delta = (uint32_t)strtoul(s, nullptr, 10);
@@ -132,10 +133,11 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
         if (o->chunk) r.chunk = o->chunk;
         if (o->local_iters) r.local_iters = o->local_iters == 0xFFFFFFFFu ? 0 : o->local_iters;
         r.timing = (o->flags & STEINER_FLAG_TIMING) != 0;
+        r.counting = (o->flags & STEINER_FLAG_COUNTERS) != 0;
     }
     if (r.delta == 0) r.delta = 1;
     if (r.block < 64 || r.block > 1024 || r.block % 64) r.block = 256;
-    if (r.driver == 2 && r.block > 512) r.block = 512;  // LDS of the persistent kernel
+    if (r.block > 256) r.block = 256;  // per-wave LDS scratch of the relaxation kernels (~10 KB per wave)
     if (r.chunk < 64) r.chunk = 64;
     if (r.grid == 0) r.grid = (uint32_t)std::max(1, g->cu_count) * 2u * (r.driver == 2 ? 1024u / r.block : 1u);
     return r;
@@ -333,6 +335,7 @@ static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t
     const double avg_deg = n ? (double)nnz / (double)n : 1.0;
     double d = 2.0 * avg_w / std::max(1.0, avg_deg);
     g->default_delta = (uint32_t)std::max(1.0, std::min(d, 4.0e9));
+    g->avg_w = avg_w;
     return STEINER_OK;
 }
 
@@ -500,6 +503,54 @@ extern "C" int steiner_solve_batch(steiner_graph *g, uint32_t q, const uint32_t 
     for (uint32_t i = 0; i < q; i++) {
         status[i] = qs[i].status;
         if (qs[i].status == STEINER_OK) outs[i] = qs[i].result.release();
+    }
+    return STEINER_OK;
+}
+
+extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint32_t k, steiner_options *out) {
+    if (!g) return fail(STEINER_EINVAL, "NULL graph");
+    std::lock_guard<std::mutex> lk(g->mu);
+    int rc = hip_check(hipSetDevice(g->device), "hipSetDevice");
+    if (rc) return rc;
+    std::vector<uint32_t> S;
+    if ((rc = canon_seeds(g, seeds, k, S))) return rc;
+    if (S.size() < 2) return fail(STEINER_EINVAL, "tuning needs at least 2 distinct seeds");
+    const double w = std::max(1.0, g->avg_w);
+    std::vector<uint32_t> deltas = {g->default_delta, (uint32_t)std::max(1.0, w / 2), (uint32_t)std::max(1.0, 2 * w),
+                                    (uint32_t)std::max(1.0, 8 * w), 0xFFFFFFFFu};
+    std::sort(deltas.begin(), deltas.end());
+    deltas.erase(std::unique(deltas.begin(), deltas.end()), deltas.end());
+    const uint32_t locals[] = {2, 8, 32};
+    double best = 1e300;
+    uint32_t best_d = g->default_delta, best_l = 8;
+    for (uint32_t d : deltas)
+        for (uint32_t l : locals) {
+            Options o = resolve_options(g, nullptr);
+            o.delta = d;
+            o.local_iters = l;
+            double t_min = 1e300;
+            for (int rep = 0; rep < 2; rep++) {
+                std::vector<Query> qs(1);
+                qs[0].S = S;
+                const auto t0 = std::chrono::steady_clock::now();
+                if ((rc = run_pass(g, o, qs))) return rc;
+                const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                if (qs[0].status && qs[0].status != STEINER_EDISCONNECTED && qs[0].status != STEINER_EOVERFLOW)
+                    return qs[0].status;
+                t_min = std::min(t_min, t);
+            }
+            if (t_min < best) {
+                best = t_min;
+                best_d = d;
+                best_l = l;
+            }
+        }
+    g->tuned_delta = best_d;
+    g->tuned_local = best_l;
+    if (out) {
+        memset(out, 0, sizeof(*out));
+        out->delta = best_d;
+        out->local_iters = best_l;
     }
     return STEINER_OK;
 }

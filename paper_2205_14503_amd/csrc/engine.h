@@ -37,7 +37,7 @@ struct HostPinned {
 
 struct Options {
     uint32_t delta, driver, block, grid, small_max, chunk, local_iters;
-    bool timing;
+    bool timing, counting;
 };
 
 // Device workspace of a multi-query pass, reused across solves of a graph.
@@ -54,6 +54,46 @@ struct Workspace {
 };
 
 enum StopAfter { STOP_NEVER = 0, STOP_AFTER_SCAN = 1, STOP_AFTER_COMPACT = 2 };
+
+// Offsets of the per-pass control region (counters, pass control, per-slot
+// arrays) for Q slots; every array starts on a 256-byte boundary.
+struct Layout {
+    size_t counters, pass, thr, thr_prev, pt_ptr, pt_len, oidx_ptr, oval_ptr, ocap, far_min, near_mark, carry, active,
+        adv, done, advances, slot_err, out_cnt, slot_ids, total;
+    explicit Layout(uint32_t Q) {
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+            size_t at = o;
+            o += (bytes + 255) & ~(size_t)255;
+            return at;
+        };
+        counters = take(sizeof(Counters));
+        pass = take(sizeof(PassCtl));
+        thr = take(8ull * Q);
+        thr_prev = take(8ull * Q);
+        pt_ptr = take(8ull * Q);
+        pt_len = take(8ull * Q);
+        oidx_ptr = take(8ull * Q);
+        oval_ptr = take(8ull * Q);
+        ocap = take(8ull * Q);
+        far_min = take(12ull * Q);
+        near_mark = take(12ull * Q);
+        carry = take(4ull * Q);
+        active = take(4ull * Q);
+        adv = take(4ull * Q);
+        done = take(4ull * Q);
+        advances = take(4ull * Q);
+        slot_err = take(4ull * Q);
+        out_cnt = take(4ull * Q);
+        slot_ids = take(4ull * Q);
+        total = o;
+    }
+};
+
+
+// VorParams of a pass whose control region starts at `ctl` (layout L).
+void bind_pass(VorParams &P, const DevGraph &dg, uint8_t *ctl, const Layout &L, uint32_t Q);
+
 
 }  // namespace stn
 
@@ -75,6 +115,9 @@ struct steiner_graph {
     stn::DevGraph dg{};
     std::vector<uint64_t> h_rp;  // host copy of the row offsets
     uint32_t default_delta = 1;
+    uint32_t tuned_delta = 0;    // set by steiner_graph_tune
+    uint32_t tuned_local = 0;
+    double avg_w = 1.0;
     int cu_count = 256;
     std::mutex mu;               // serialises solves on this graph
     stn::Workspace ws;
@@ -97,6 +140,12 @@ struct Query {
 
 Options resolve_options(const steiner_graph *g, const steiner_options *o);
 int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs);
+// Steps 3-7 of one query whose G'1 entries (pidx, pval) are on the host and
+// whose keys / preds are on the device: MST, pruning, expansion, D.
+int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, const uint32_t *pred, uint32_t k,
+                 const std::vector<uint32_t> &pidx, const std::vector<uint64_t> &pval, DevBuf &sel_buf,
+                 uint32_t *visited, uint32_t *oedges, std::unique_ptr<steiner_result> &out, double *ms_mst,
+                 double *ms_expand);
 int prim_mst(uint32_t k, const std::vector<uint32_t> &pidx, const std::vector<uint64_t> &pval,
              std::vector<uint32_t> &chosen);
 void pair_from_index(uint64_t p, uint32_t *i, uint32_t *j);

@@ -115,6 +115,7 @@ DEVI void append_b(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, 
 // long shortest paths (high-diameter graphs otherwise need a global round per
 // hop).  Anything the queue cannot hold goes to the next round's list.
 constexpr uint32_t LQ_CAP = 256;
+constexpr uint32_t OUT_CAP = 256;
 
 struct WaveScratch {
     uint32_t incl[64];
@@ -122,87 +123,156 @@ struct WaveScratch {
     uint32_t slot[64];
     uint32_t pad[64];
     uint64_t key[64];
-    uint64_t lq[LQ_CAP];
+    // local queue: item (slot << 32 | v), the key it was improved to, its row extent
+    uint64_t lq_item[LQ_CAP];
+    uint64_t lq_key[LQ_CAP];
+    uint32_t lq_beg[LQ_CAP];
+    uint32_t lq_deg[LQ_CAP];
+    // staging for the next round's S list: one global atomicAdd per flush
+    // instead of one per 64-edge step (the list counter is a single address)
+    uint64_t out[OUT_CAP];
+    uint32_t out_n;
+    uint32_t ev[EV_N];  // per-wave event counts (counting mode)
 };
 
-// Relax one edge (src key ksrc, target u, weight w) of query `slot` and
-// schedule u if its key improved: into the wave's local queue (lq != null,
-// small row, room left), else into the next round's list once per round
-// (stamp), or park it if its distance is beyond the query's bucket.  Must be
-// reached by every lane of the wave.
-DEVI void relax_push(const VorParams &P, const RoundIdx &R, const uint64_t *thr, bool valid, uint32_t slot,
-                     uint64_t ksrc, uint32_t u, uint32_t w, uint64_t *lq, uint32_t &lq_head, uint32_t &lq_tail) {
-    const uint32_t n = P.g.n;
-    bool improved = false;
-    uint32_t nd = 0;
-    if (valid) {
-        uint64_t d = (ksrc >> 32) + (uint64_t)w;
-        if (d < DIST_INF) {  // a distance of 2^32-1 or more is never stored
-            uint64_t cand = (d << 32) | (ksrc & 0xFFFFFFFFull);
-            uint64_t *kp = P.key + (size_t)slot * n + u;
-            if (cand < *kp) {  // possibly stale (larger) value: filter only
-                uint64_t old = atomicMin((unsigned long long *)kp, (unsigned long long)cand);
-                if (cand < old) {
-                    improved = true;
-                    nd = (uint32_t)d;
-                }
-            }
-        }
-    }
-    bool near = false, park = false;
-    uint32_t deg = 0;
-    if (improved) {
-        if ((uint64_t)nd < thr[slot]) {
-            near = true;
-            deg = P.g.rp[u + 1] - P.g.rp[u];
-        } else {
-            park = true;
-        }
-    }
-    if (park) {
-        P.dirty[(size_t)slot * n + u] = 1;
-        uint32_t *fm = P.far_min + (size_t)R.b * P.nslots + slot;
-        if (nd < *fm) atomicMin(fm, nd);
-    }
-    bool local = false;
-    if (lq) {
-        const bool want = near && deg <= P.small_max;
-        const uint64_t m = __ballot(want);
-        if (m) {
-            const uint32_t space = LQ_CAP - (lq_tail - lq_head);
-            const uint32_t rank = lanes_below(m);
-            local = want && rank < space;
-            if (local) lq[(lq_tail + rank) % LQ_CAP] = s_item(slot, u);
-            lq_tail += min((uint32_t)__popcll(m), space);
-        }
-    }
-    bool claim = false;
-    if (near && !local) {
-        uint32_t *sp = P.aux + (size_t)slot * n + u;
-        if (atomicExch(sp, R.r + 1) != R.r + 1) {
-            claim = true;
-            uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + slot;
-            if (*nm == 0) *nm = 1;
-        }
-    }
-    append_s(P, R.nxt, R.c_nxt, claim && deg <= P.small_max, s_item(slot, u));
-    append_b(P, R.nxt, R.c_nxt, claim && deg > P.small_max, slot, u, deg);
+DEVI void count(const VorParams &P, WaveScratch *L, int which, bool pred) {
+    if (!P.counting) return;
+    const uint64_t m = __ballot(pred);
+    if (lane() == 0 && m) L->ev[which] += (uint32_t)__popcll(m);
 }
 
-// Expands one frontier item per lane (lanes with `has`): all edges of the
-// items' rows, 64 edges per step, balanced across the wave by a prefix sum of
-// the degrees (coalesced 8-byte (col, w) loads within each row).
-DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *thr, bool has, uint32_t slot,
-                       uint32_t v, WaveScratch *L, bool use_lq, uint32_t &lq_head, uint32_t &lq_tail) {
-    const uint32_t ln = lane();
-    uint32_t beg = 0, deg = 0;
-    uint64_t kv = KEY_INF;
-    if (has) {
-        kv = ld_agent(P.key + (size_t)slot * P.g.n + v);
-        beg = P.g.rp[v];
-        deg = P.g.rp[v + 1] - beg;
-        if (kv == KEY_INF) deg = 0;
+// Moves the wave's staged S items to the next round's list.
+DEVI void flush_out(const VorParams &P, const RoundIdx &R, WaveScratch *L) {
+    wave_sync();
+    const uint32_t cnt = L->out_n;
+    if (cnt == 0) return;
+    uint32_t base = 0;
+    if (lane() == 0) base = atomicAdd(&P.cnt->s[R.c_nxt], cnt);
+    base = __shfl(base, 0, 64);
+    for (uint32_t i = lane(); i < cnt; i += 64) {
+        if (base + i < P.cap_s) P.items_s[R.nxt][base + i] = L->out[i];
+        else atomicOr(&P.pass->err, ERR_LIST_OVERFLOW);
     }
+    wave_sync();
+    if (lane() == 0) L->out_n = 0;
+    wave_sync();
+}
+
+// Stages S items of the lanes with `pred` (flushing first when full).
+DEVI void stage_s(const VorParams &P, const RoundIdx &R, WaveScratch *L, bool pred, uint64_t item) {
+    const uint64_t m = __ballot(pred);
+    if (m == 0) return;
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    wave_sync();
+    if (L->out_n + cnt > OUT_CAP) flush_out(P, R, L);
+    const uint32_t at = L->out_n;
+    if (pred) L->out[at + lanes_below(m)] = item;
+    wave_sync();
+    if (lane() == 0) L->out_n = at + cnt;
+    wave_sync();
+}
+
+constexpr int UNROLL = 4;  // independent 64-edge steps whose memory operations are issued together
+
+// Relax UNROLL edges per lane (src key ksrc[i], target u[i], weight w[i] of
+// query slot[i]; lanes/steps with valid[i] false do nothing) and schedule
+// every improved target: into the wave's local queue (L != null, small row,
+// room left) together with its improved key and row extent, else into the
+// next round's list once per round (stamp), or park it if its distance is
+// beyond the query's bucket.  The loads, atomics and row-offset reads of the
+// UNROLL steps are independent and issued back to back, so one memory
+// latency chain covers 64 * UNROLL edges.  Must be reached by every lane.
+DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr, const bool *valid,
+                      const uint32_t *slot, const uint64_t *ksrc, const uint32_t *u, const uint32_t *w, WaveScratch *Lw,
+                      bool use_lq, uint32_t &lq_head, uint32_t &lq_tail) {
+    WaveScratch *L = use_lq ? Lw : nullptr;
+    const uint32_t n = P.g.n;
+    uint64_t cand[UNROLL], cur[UNROLL];
+    bool live[UNROLL], improved[UNROLL];
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        const uint64_t d = (ksrc[i] >> 32) + (uint64_t)w[i];
+        live[i] = valid[i] && d < DIST_INF;  // a distance of 2^32-1 or more is never stored
+        cand[i] = (d << 32) | (ksrc[i] & 0xFFFFFFFFull);
+    }
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++)  // possibly stale (larger) values: filter only
+        cur[i] = live[i] ? P.key[(size_t)slot[i] * n + u[i]] : 0;
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        count(P, Lw, EV_ATTEMPT, valid[i]);
+        count(P, Lw, EV_ATOMIC, live[i] && cand[i] < cur[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        improved[i] = false;
+        if (live[i] && cand[i] < cur[i]) {
+            const uint64_t old = atomicMin((unsigned long long *)(P.key + (size_t)slot[i] * n + u[i]),
+                                           (unsigned long long)cand[i]);
+            improved[i] = cand[i] < old;
+        }
+    }
+    bool near[UNROLL];
+    uint32_t beg[UNROLL], deg[UNROLL];
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        const uint32_t nd = (uint32_t)(cand[i] >> 32);
+        near[i] = improved[i] && (uint64_t)nd < thr[slot[i]];
+        beg[i] = near[i] ? P.g.rp[u[i]] : 0;
+        deg[i] = near[i] ? P.g.rp[u[i] + 1] : 0;
+        if (improved[i] && !near[i]) {  // park until the query's bucket reaches it
+            P.dirty[(size_t)slot[i] * n + u[i]] = 1;
+            uint32_t *fm = P.far_min + (size_t)R.b * P.nslots + slot[i];
+            if (nd < *fm) atomicMin(fm, nd);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        deg[i] -= beg[i];
+        bool local = false;
+        if (L) {
+            const bool want = near[i] && deg[i] <= P.small_max;
+            const uint64_t m = __ballot(want);
+            if (m) {
+                const uint32_t space = LQ_CAP - (lq_tail - lq_head);
+                const uint32_t rank = lanes_below(m);
+                local = want && rank < space;
+                if (local) {
+                    const uint32_t at = (lq_tail + rank) % LQ_CAP;
+                    L->lq_item[at] = s_item(slot[i], u[i]);
+                    L->lq_key[at] = cand[i];
+                    L->lq_beg[at] = beg[i];
+                    L->lq_deg[at] = deg[i];
+                }
+                lq_tail += min((uint32_t)__popcll(m), space);
+            }
+        }
+        count(P, Lw, EV_IMPROVED, improved[i]);
+        count(P, Lw, EV_LOCAL, local);
+        count(P, Lw, EV_PARK, improved[i] && !near[i]);
+        bool claim = false;
+        if (near[i] && !local) {
+            if (atomicExch(P.aux + (size_t)slot[i] * n + u[i], R.r + 1) != R.r + 1) {
+                claim = true;
+                uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + slot[i];
+                if (*nm == 0) *nm = 1;
+            }
+        }
+        count(P, Lw, EV_GLOBAL, claim);
+        stage_s(P, R, Lw, claim && deg[i] <= P.small_max, s_item(slot[i], u[i]));
+        append_b(P, R.nxt, R.c_nxt, claim && deg[i] > P.small_max, slot[i], u[i], deg[i]);
+    }
+}
+
+// Expands one frontier item per lane: the row [beg, beg + deg) of a vertex
+// with key kv in query `slot` (deg = 0 for idle lanes), 64 * UNROLL edges per
+// step, balanced across the wave by a prefix sum of the degrees (coalesced
+// 8-byte (col, w) loads within each row).
+DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t slot, uint64_t kv,
+                       uint32_t beg, uint32_t deg, WaveScratch *L, bool use_lq, uint32_t &lq_head,
+                       uint32_t &lq_tail) {
+    const uint32_t ln = lane();
+    count(P, L, EV_ITEMS, kv != KEY_INF);
     const uint32_t incl = wave_incl_scan(deg);
     const uint32_t total = __shfl(incl, 63, 64);
     wave_sync();
@@ -211,23 +281,35 @@ DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *th
     L->slot[ln] = slot;
     L->key[ln] = kv;
     wave_sync();
-    uint64_t *lq = use_lq ? L->lq : nullptr;
-    for (uint32_t base = 0; base < total; base += 64) {
-        const uint32_t t = base + ln;
-        const bool valid = t < total;
-        uint32_t j = 0;
-        if (valid) {
-            uint32_t lo = 0, hi = 63;
-            while (lo < hi) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (L->incl[mid] > t) hi = mid; else lo = mid + 1;
+    for (uint32_t base = 0; base < total; base += 64 * UNROLL) {
+        bool valid[UNROLL];
+        uint32_t sl[UNROLL], uu[UNROLL], ww[UNROLL], e[UNROLL];
+        uint64_t ks[UNROLL];
+#pragma unroll
+        for (int i = 0; i < UNROLL; i++) {
+            const uint32_t t = base + 64 * i + ln;
+            valid[i] = t < total;
+            uint32_t j = 0;
+            if (valid[i]) {
+                uint32_t lo = 0, hi = 63;
+                while (lo < hi) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (L->incl[mid] > t) hi = mid; else lo = mid + 1;
+                }
+                j = lo;
             }
-            j = lo;
+            const uint32_t ex = j ? L->incl[j - 1] : 0;
+            e[i] = L->beg[j] + (t - ex);
+            sl[i] = L->slot[j];
+            ks[i] = L->key[j];
         }
-        const uint32_t ex = j ? L->incl[j - 1] : 0;
-        uint2 a = make_uint2(0, 0);
-        if (valid) a = P.g.adj[L->beg[j] + (t - ex)];
-        relax_push(P, R, thr, valid, L->slot[j], L->key[j], a.x, a.y, lq, lq_head, lq_tail);
+#pragma unroll
+        for (int i = 0; i < UNROLL; i++) {
+            const uint2 a = valid[i] ? P.g.adj[e[i]] : make_uint2(0, 0);
+            uu[i] = a.x;
+            ww[i] = a.y;
+        }
+        relax_multi(P, R, thr, valid, sl, ks, uu, ww, L, use_lq, lq_head, lq_tail);
     }
 }
 
@@ -243,33 +325,47 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
     const uint32_t lim = P.g.rp[v + 1];
     uint32_t end = (lim - beg > P.chunk) ? beg + P.chunk : lim;
     if (kv == KEY_INF) end = beg;
-    uint64_t *lq = use_lq ? L->lq : nullptr;
-    for (uint32_t e0 = beg; e0 < end; e0 += 64) {
-        const uint32_t e = e0 + lane();
-        const bool valid = e < end;
-        uint2 a = make_uint2(0, 0);
-        if (valid) a = P.g.adj[e];
-        relax_push(P, R, thr, valid, slot, kv, a.x, a.y, lq, lq_head, lq_tail);
+    for (uint32_t e0 = beg; e0 < end; e0 += 64 * UNROLL) {
+        bool valid[UNROLL];
+        uint32_t sl[UNROLL], uu[UNROLL], ww[UNROLL];
+        uint64_t ks[UNROLL];
+#pragma unroll
+        for (int i = 0; i < UNROLL; i++) {
+            const uint64_t e = (uint64_t)e0 + 64 * i + lane();
+            valid[i] = e < end;
+            const uint2 a = valid[i] ? P.g.adj[e] : make_uint2(0, 0);
+            uu[i] = a.x;
+            ww[i] = a.y;
+            sl[i] = slot;
+            ks[i] = kv;
+        }
+        relax_multi(P, R, thr, valid, sl, ks, uu, ww, L, use_lq, lq_head, lq_tail);
     }
 }
 
-// Expand the wave's local queue for at most `budget` batches of 64, then move
-// what is left to the next round's list (once per vertex per round).
+// Expand the wave's local queue for at most `budget` batches of 64 (each
+// entry carries the key it was improved to: a later improvement of the same
+// vertex queues or lists it again), then move what is left to the next
+// round's list (once per vertex per round; that path re-reads the key).
 DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr, WaveScratch *L, uint32_t budget,
                       uint32_t &h, uint32_t &t) {
     for (uint32_t it = 0; it < budget && h != t; it++) {
         const uint32_t take = min(t - h, 64u);
         wave_sync();
         const bool has = lane() < take;
-        const uint64_t item = has ? L->lq[(h + lane()) % LQ_CAP] : 0;
+        const uint32_t at = (h + lane()) % LQ_CAP;
+        const uint64_t item = has ? L->lq_item[at] : 0;
+        const uint64_t kv = has ? L->lq_key[at] : KEY_INF;
+        const uint32_t beg = has ? L->lq_beg[at] : 0;
+        const uint32_t deg = has ? L->lq_deg[at] : 0;
         h += take;
-        expand_items(P, R, thr, has, (uint32_t)(item >> 32), (uint32_t)item, L, true, h, t);
+        expand_items(P, R, thr, (uint32_t)(item >> 32), kv, beg, deg, L, true, h, t);
     }
     while (h != t) {
         const uint32_t take = min(t - h, 64u);
         wave_sync();
         const bool has = lane() < take;
-        const uint64_t item = has ? L->lq[(h + lane()) % LQ_CAP] : 0;
+        const uint64_t item = has ? L->lq_item[(h + lane()) % LQ_CAP] : 0;
         h += take;
         bool claim = false;
         if (has) {
@@ -280,7 +376,7 @@ DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr
                 if (*nm == 0) *nm = 1;
             }
         }
-        append_s(P, R.nxt, R.c_nxt, claim, item);
+        stage_s(P, R, L, claim, item);
     }
 }
 
@@ -289,17 +385,36 @@ DEVI void relax_round_body(const VorParams &P, const RoundIdx &R, const uint64_t
     const uint32_t ng = (cs + 63) / 64;
     const uint32_t units = ng + cb;
     const bool use_lq = P.local_iters != 0;
+    if (lane() == 0) {
+        L->out_n = 0;
+        for (int i = 0; i < EV_N; i++) L->ev[i] = 0;
+    }
+    wave_sync();
     for (uint32_t u = wave_gid; u < units; u += nwaves) {
         uint32_t h = 0, t = 0;
         if (u < ng) {
             const uint32_t idx = u * 64 + lane();
-            const bool has = idx < cs;
-            const uint64_t it = has ? P.items_s[R.cur][idx] : 0;
-            expand_items(P, R, thr, has, (uint32_t)(it >> 32), (uint32_t)it, L, use_lq, h, t);
+            uint32_t slot = 0, beg = 0, deg = 0;
+            uint64_t kv = KEY_INF;
+            if (idx < cs) {
+                const uint64_t it = P.items_s[R.cur][idx];
+                slot = (uint32_t)(it >> 32);
+                const uint32_t v = (uint32_t)it;
+                kv = ld_agent(P.key + (size_t)slot * P.g.n + v);
+                beg = P.g.rp[v];
+                deg = kv == KEY_INF ? 0 : P.g.rp[v + 1] - beg;
+            }
+            expand_items(P, R, thr, slot, kv, beg, deg, L, use_lq, h, t);
         } else {
             process_b_chunk(P, R, thr, u - ng, L, use_lq, h, t);
         }
         if (use_lq) drain_local(P, R, thr, L, P.local_iters, h, t);
+        flush_out(P, R, L);
+    }
+    if (P.counting && lane() < EV_N) {
+        wave_sync();
+        const uint32_t c = L->ev[lane()];
+        if (c) atomicAdd(&P.cnt->ev[lane()], (unsigned long long)c);
     }
 }
 
@@ -562,6 +677,7 @@ __global__ void k_pass_reset(VorParams P) {
         P.cnt->bar_gen = 0;
         P.cnt->abort = 0;
         P.cnt->blocks_done = 0;
+        for (int i = 0; i < EV_N; i++) P.cnt->ev[i] = 0;
     }
     for (uint32_t q = t; q < P.nslots; q += gridDim.x * blockDim.x) {
         for (int b = 0; b < 3; b++) {

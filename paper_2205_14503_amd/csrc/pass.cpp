@@ -18,40 +18,23 @@ uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chu
     return t;
 }
 
-namespace {
+void bind_pass(VorParams &P, const DevGraph &dg, uint8_t *ctl, const Layout &L, uint32_t Q) {
+    P.g = dg;
+    P.cnt = (Counters *)(ctl + L.counters);
+    P.pass = (PassCtl *)(ctl + L.pass);
+    P.far_min = (uint32_t *)(ctl + L.far_min);
+    P.near_mark = (uint32_t *)(ctl + L.near_mark);
+    P.slot.thr = (uint64_t *)(ctl + L.thr);
+    P.slot.thr_prev = (uint64_t *)(ctl + L.thr_prev);
+    P.slot.carry = (uint32_t *)(ctl + L.carry);
+    P.slot.active = (uint32_t *)(ctl + L.active);
+    P.slot.adv = (uint32_t *)(ctl + L.adv);
+    P.slot.done = (uint32_t *)(ctl + L.done);
+    P.slot.advances = (uint32_t *)(ctl + L.advances);
+    P.nslots = Q;
+}
 
-struct Layout {
-    size_t counters, pass, thr, thr_prev, pt_ptr, pt_len, oidx_ptr, oval_ptr, ocap, far_min, near_mark, carry, active,
-        adv, done, advances, slot_err, out_cnt, slot_ids, total;
-    explicit Layout(uint32_t Q) {
-        size_t o = 0;
-        auto take = [&](size_t bytes) {
-            size_t at = o;
-            o += (bytes + 255) & ~(size_t)255;
-            return at;
-        };
-        counters = take(sizeof(Counters));
-        pass = take(sizeof(PassCtl));
-        thr = take(8ull * Q);
-        thr_prev = take(8ull * Q);
-        pt_ptr = take(8ull * Q);
-        pt_len = take(8ull * Q);
-        oidx_ptr = take(8ull * Q);
-        oval_ptr = take(8ull * Q);
-        ocap = take(8ull * Q);
-        far_min = take(12ull * Q);
-        near_mark = take(12ull * Q);
-        carry = take(4ull * Q);
-        active = take(4ull * Q);
-        adv = take(4ull * Q);
-        done = take(4ull * Q);
-        advances = take(4ull * Q);
-        slot_err = take(4ull * Q);
-        out_cnt = take(4ull * Q);
-        slot_ids = take(4ull * Q);
-        total = o;
-    }
-};
+namespace {
 
 struct Timer {
     bool on;
@@ -78,6 +61,70 @@ struct Timer {
 };
 
 }  // namespace
+
+int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, const uint32_t *pred, uint32_t k,
+                 const std::vector<uint32_t> &pidx, const std::vector<uint64_t> &pval, DevBuf &sel_buf,
+                 uint32_t *visited, uint32_t *oedges, std::unique_ptr<steiner_result> &out, double *ms_mst,
+                 double *ms_expand) {
+    const uint32_t n = g->n;
+    int rc;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<uint32_t> chosen;
+    const int mrc = prim_mst(k, pidx, pval, chosen);  // Step 3
+    const auto t1 = std::chrono::steady_clock::now();
+    if (ms_mst) *ms_mst += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (mrc) return fail(mrc, "seeds are not connected");
+    // Step 4: the cross-cell edge kept for each MST pair; Steps 5-6 on the device.
+    std::vector<uint32_t> sel(chosen.size());
+    for (size_t t = 0; t < chosen.size(); t++) sel[t] = (uint32_t)(pval[chosen[t]] & 0xFFFFFFFFu);
+    if ((rc = sel_buf.ensure(sel.size() * 4 + 4))) return rc;
+    ExpandParams EP{};
+    EP.g = g->dg;
+    EP.key = key;
+    EP.pred = pred;
+    EP.sel_e = sel_buf.as<uint32_t>();
+    EP.nsel = (uint32_t)sel.size();
+    EP.visited = visited;
+    EP.oa = oedges;
+    EP.ob = oedges + n;
+    EP.ow = oedges + 2 * (size_t)n;
+    EP.ocnt = oedges + 3 * (size_t)n;
+    rc = hip_check(hipMemcpyAsync(sel_buf.ptr, sel.data(), sel.size() * 4, hipMemcpyHostToDevice, st), "H2D sel");
+    if (!rc) rc = hip_check(launch_fill_u32(EP.visited, ((size_t)n + 31) / 32, 0u, st), "visited");
+    if (!rc) rc = hip_check(launch_fill_u32(EP.ocnt, 1, 0u, st), "count");
+    if (!rc) rc = hip_check(launch_expand(EP, st), "expand");
+    uint32_t m_out = 0;
+    if (!rc) rc = hip_check(hipMemcpyAsync(&m_out, EP.ocnt, 4, hipMemcpyDeviceToHost, st), "D2H count");
+    if (!rc) rc = hip_check(hipStreamSynchronize(st), "expand sync");
+    if (rc) return rc;
+    if (m_out > n) return fail(STEINER_EDEVICE, "expansion overflow");
+    std::vector<uint32_t> a(m_out), b(m_out), w(m_out);
+    rc = hip_check(hipMemcpyAsync(a.data(), EP.oa, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+    if (!rc) rc = hip_check(hipMemcpyAsync(b.data(), EP.ob, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+    if (!rc) rc = hip_check(hipMemcpyAsync(w.data(), EP.ow, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+    if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H edges");
+    if (rc) return rc;
+    // Step 7: canonical order (a, b, w) and D
+    std::vector<std::tuple<uint32_t, uint32_t, uint32_t>> ed(m_out);
+    for (uint32_t t = 0; t < m_out; t++) ed[t] = std::make_tuple(a[t], b[t], w[t]);
+    std::sort(ed.begin(), ed.end());
+    std::unique_ptr<steiner_result> res(new steiner_result());
+    res->a.resize(m_out);
+    res->b.resize(m_out);
+    res->w.resize(m_out);
+    uint64_t D = 0;
+    for (uint32_t t = 0; t < m_out; t++) {
+        res->a[t] = std::get<0>(ed[t]);
+        res->b[t] = std::get<1>(ed[t]);
+        res->w[t] = std::get<2>(ed[t]);
+        D += res->w[t];
+    }
+    res->total = D;
+    res->stats.tree_edges = m_out;
+    out = std::move(res);
+    if (ms_expand) *ms_expand += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+    return STEINER_OK;
+}
 
 int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     const auto t_start = std::chrono::steady_clock::now();
@@ -128,7 +175,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     uint8_t *hctl = ws.host.as<uint8_t>();
 
     VorParams P{};
-    P.g = g->dg;
+    bind_pass(P, g->dg, ctl, L, Q);
     P.key = ws.key.as<uint64_t>();
     P.aux = ws.aux.as<uint32_t>();
     P.dirty = ws.dirty.as<uint8_t>();
@@ -138,22 +185,11 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     P.items_b[1] = ws.items_b[1].as<uint64_t>();
     P.cap_s = (uint32_t)cap_s;
     P.cap_b = (uint32_t)cap_b;
-    P.cnt = (Counters *)(ctl + L.counters);
-    P.pass = (PassCtl *)(ctl + L.pass);
-    P.far_min = (uint32_t *)(ctl + L.far_min);
-    P.near_mark = (uint32_t *)(ctl + L.near_mark);
-    P.slot.thr = (uint64_t *)(ctl + L.thr);
-    P.slot.thr_prev = (uint64_t *)(ctl + L.thr_prev);
-    P.slot.carry = (uint32_t *)(ctl + L.carry);
-    P.slot.active = (uint32_t *)(ctl + L.active);
-    P.slot.adv = (uint32_t *)(ctl + L.adv);
-    P.slot.done = (uint32_t *)(ctl + L.done);
-    P.slot.advances = (uint32_t *)(ctl + L.advances);
-    P.nslots = Q;
     P.delta = o.delta;
     P.small_max = o.small_max;
     P.chunk = o.chunk;
     P.local_iters = o.local_iters;
+    P.counting = o.counting ? 1u : 0u;
 
     // Per-slot pointer tables (host image, then one copy).
     {
@@ -308,6 +344,10 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
                         "D2H counts")))
         return rc;
     if ((rc = hip_check(hipMemcpyAsync(hpass, P.pass, sizeof(PassCtl), hipMemcpyDeviceToHost, st), "D2H pass"))) return rc;
+    Counters hcnt{};
+    if (o.counting &&
+        (rc = hip_check(hipMemcpyAsync(&hcnt, P.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st), "D2H counters")))
+        return rc;
     if ((rc = hip_check(hipStreamSynchronize(st), "compact sync"))) return rc;
     if (hpass->err & ERR_LIST_OVERFLOW) return fail(STEINER_EDEVICE, "compaction overflow");
     const uint32_t *h_err = (const uint32_t *)(hctl + L.slot_err);
@@ -346,69 +386,18 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
             if (rc) return rc;
         }
         if (qq.stop_after == STOP_AFTER_COMPACT) continue;
-        const auto t0 = std::chrono::steady_clock::now();
-        std::vector<uint32_t> chosen;
-        int mrc = prim_mst(k, qq.pidx, qq.pval, chosen);
-        const auto t1 = std::chrono::steady_clock::now();
-        ms_mst += std::chrono::duration<double, std::milli>(t1 - t0).count();
-        if (mrc) {
-            qq.status = fail(mrc, "seeds are not connected");
+        uint32_t *oe = ws.oedges.as<uint32_t>();
+        int trc = tree_from_g1(g, st, P.key + (size_t)s * n, P.aux + (size_t)s * n, k, qq.pidx, qq.pval, ws.sel,
+                               ws.visited.as<uint32_t>(), oe, qq.result, &ms_mst, &ms_expand);
+        if (trc == STEINER_EDISCONNECTED) {
+            qq.status = trc;
             continue;
         }
-        // Step 4: the cross-cell edge kept for each MST pair; Steps 5-6 on the device.
-        std::vector<uint32_t> sel(chosen.size());
-        for (size_t t = 0; t < chosen.size(); t++) sel[t] = (uint32_t)(qq.pval[chosen[t]] & 0xFFFFFFFFu);
-        if ((rc = ws.sel.ensure(sel.size() * 4 + 4))) return rc;
-        uint32_t *oe = ws.oedges.as<uint32_t>();
-        ExpandParams EP{};
-        EP.g = g->dg;
-        EP.key = P.key + (size_t)s * n;
-        EP.pred = P.aux + (size_t)s * n;
-        EP.sel_e = ws.sel.as<uint32_t>();
-        EP.nsel = (uint32_t)sel.size();
-        EP.visited = ws.visited.as<uint32_t>();
-        EP.oa = oe;
-        EP.ob = oe + n;
-        EP.ow = oe + 2 * (size_t)n;
-        EP.ocnt = oe + 3 * (size_t)n;
-        rc = hip_check(hipMemcpyAsync(ws.sel.ptr, sel.data(), sel.size() * 4, hipMemcpyHostToDevice, st), "H2D sel");
-        if (!rc) rc = hip_check(launch_fill_u32(EP.visited, ((size_t)n + 31) / 32, 0u, st), "visited");
-        if (!rc) rc = hip_check(launch_fill_u32(EP.ocnt, 1, 0u, st), "count");
-        if (!rc) rc = hip_check(launch_expand(EP, st), "expand");
-        uint32_t m_out = 0;
-        if (!rc) rc = hip_check(hipMemcpyAsync(&m_out, EP.ocnt, 4, hipMemcpyDeviceToHost, st), "D2H count");
-        if (!rc) rc = hip_check(hipStreamSynchronize(st), "expand sync");
-        if (rc) return rc;
-        if (m_out > n) return fail(STEINER_EDEVICE, "expansion overflow");
-        std::unique_ptr<steiner_result> res(new steiner_result());
-        std::vector<uint32_t> a(m_out), b(m_out), w(m_out);
-        rc = hip_check(hipMemcpyAsync(a.data(), EP.oa, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
-        if (!rc) rc = hip_check(hipMemcpyAsync(b.data(), EP.ob, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
-        if (!rc) rc = hip_check(hipMemcpyAsync(w.data(), EP.ow, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
-        if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H edges");
-        if (rc) return rc;
-        const auto t2 = std::chrono::steady_clock::now();
-        ms_expand += std::chrono::duration<double, std::milli>(t2 - t1).count();
-        // Step 7: canonical order (a, b, w) and D
-        std::vector<std::tuple<uint32_t, uint32_t, uint32_t>> ed(m_out);
-        for (uint32_t t = 0; t < m_out; t++) ed[t] = std::make_tuple(a[t], b[t], w[t]);
-        std::sort(ed.begin(), ed.end());
-        res->a.resize(m_out);
-        res->b.resize(m_out);
-        res->w.resize(m_out);
-        uint64_t D = 0;
-        for (uint32_t t = 0; t < m_out; t++) {
-            res->a[t] = std::get<0>(ed[t]);
-            res->b[t] = std::get<1>(ed[t]);
-            res->w[t] = std::get<2>(ed[t]);
-            D += res->w[t];
-        }
-        res->total = D;
-        res->stats.rounds = rounds;
-        res->stats.advances = slot_adv[s];
-        res->stats.pairs = m;
-        res->stats.tree_edges = m_out;
-        qq.result = std::move(res);
+        if (trc) return trc;
+        steiner_stats &x = qq.result->stats;
+        x.rounds = rounds;
+        x.advances = slot_adv[s];
+        x.pairs = m;
     }
     const auto t_end = std::chrono::steady_clock::now();
     const double ms_total = std::chrono::duration<double, std::milli>(t_end - t_start).count();
@@ -425,6 +414,13 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         x.ms_total = ms_total;
         x.ms_relax_kernels = ms_relax;
         x.relax_launches = relax_launches;
+        x.relax_attempts = hcnt.ev[EV_ATTEMPT];
+        x.relax_atomics = hcnt.ev[EV_ATOMIC];
+        x.relax_improved = hcnt.ev[EV_IMPROVED];
+        x.pushes_local = hcnt.ev[EV_LOCAL];
+        x.pushes_next = hcnt.ev[EV_GLOBAL];
+        x.parked = hcnt.ev[EV_PARK];
+        x.items = hcnt.ev[EV_ITEMS];
     }
     return STEINER_OK;
 }

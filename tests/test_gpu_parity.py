@@ -181,6 +181,21 @@ def test_grid2048_full_size(stream):
             assert np.array_equal(pred, ref.pred)
 
 
+def test_tune_keeps_results(stream):
+    g = W.rmat(14, 16, wlo=1, whi=1000)
+    seeds = W.sample(W.lcc(g), 200, master=8)
+    ref = O.solve(g, seeds)
+    with st.Graph(g, 0, stream) as dg:
+        say("autotune")
+        chosen = dg.tune(seeds)
+        assert chosen["delta"] >= 1
+        tree = dg.solve(seeds)
+        assert tree.edges == ref.edges and tree.total == ref.total
+        other = W.sample(W.lcc(g), 77, master=9)
+        assert dg.solve(other).edges == O.solve(g, other).edges
+        assert gpu_code(dg.tune, [5])[0] == st.EINVAL
+
+
 def test_batch_equals_single_and_oracle(stream):
     g = W.rmat(14, 16, wlo=1, whi=1000)
     cand = W.lcc(g)

@@ -1,0 +1,129 @@
+"""Continuous-batching server: every result in the mix equals the result of
+the same query alone and the oracle's, admission respects the memory budget,
+and error paths report the right codes."""
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2205_14503_amd as st
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def graph():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    torch.cuda.set_device(0)
+    g = W.rmat(15, 16, wlo=1, whi=1000)
+    cand = W.lcc(g)
+    dg = st.Graph(g, 0, torch.cuda.current_stream())
+    yield g, cand, dg
+    dg.close()
+
+
+def test_server_mix_equals_alone_and_oracle(graph):
+    g, cand, dg = graph
+    ks = [3, 40, 2, 600, 17, 5, 250, 1, 90, 8, 33, 1200, 4, 64, 7, 150]
+    sets = [W.sample(cand, k, master=11, stream=300 + q) for q, k in enumerate(ks)]
+    say("server: 16 queries, 5 slots")
+    srv = st.steiner_server_create(dg.handle, 4 << 30, 5)
+    try:
+        tickets = [st.steiner_server_submit(srv, s) for s in sets]
+        trees = [st.steiner_server_wait(srv, t) for t in tickets]
+    finally:
+        st.steiner_server_destroy(srv)
+    for q, (s, tree) in enumerate(zip(sets, trees)):
+        ref = O.solve(g, s)
+        assert ref.code == O.OK
+        assert tree.edges == ref.edges and tree.total == ref.total, f"query {q} (k={ks[q]})"
+        alone = dg.solve(s)
+        assert alone.edges == tree.edges
+
+
+def test_server_concurrent_clients(graph):
+    g, cand, dg = graph
+    sets = [W.sample(cand, int(k), master=12, stream=400 + q) for q, k in enumerate(W.log_uniform_sizes(24, 3, 300, 5))]
+    refs = [dg.solve(s) for s in sets]
+    say("server: 4 client threads, 24 queries")
+    srv = st.steiner_server_create(dg.handle, 8 << 30, 8)
+    out = [None] * len(sets)
+    errors = []
+
+    def client(idx):
+        try:
+            for q in idx:
+                t = st.steiner_server_submit(srv, sets[q])
+                out[q] = st.steiner_server_wait(srv, t)
+        except Exception as e:  # pragma: no cover - reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=client, args=(list(range(i, len(sets), 4)),)) for i in range(4)]
+    try:
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(timeout=120)
+    finally:
+        st.steiner_server_destroy(srv)
+    assert not errors, errors
+    for q in range(len(sets)):
+        assert out[q] is not None and out[q].edges == refs[q].edges, f"query {q}"
+
+
+def test_server_budget_and_errors(graph):
+    g, cand, dg = graph
+    one = 13 * g.n
+    srv = st.steiner_server_create(dg.handle, 3 * one + (1 << 20), 64)
+    try:
+        need = st.steiner_server_query_bytes(srv, 100)
+        assert need >= one + 8 * 100 * 99 // 2
+        # a query that alone exceeds the budget is refused at submit
+        with pytest.raises(st.SteinerError) as e:
+            st.steiner_server_submit(srv, cand[:3000])
+        assert e.value.code == st.ENOMEM
+        with pytest.raises(st.SteinerError) as e:
+            st.steiner_server_submit(srv, [g.n + 5])
+        assert e.value.code == st.EINVAL
+        # k = 1 completes at once
+        t = st.steiner_server_submit(srv, [int(cand[0])] * 4)
+        tree = st.steiner_server_wait(srv, t, 10_000_000)
+        assert tree.total == 0 and len(tree.a) == 0
+        # at most 3 queries fit the budget at a time; all still finish correctly
+        sets = [W.sample(cand, 20, master=13, stream=500 + q) for q in range(9)]
+        tickets = [st.steiner_server_submit(srv, s) for s in sets]
+        for s, t in zip(sets, tickets):
+            assert st.steiner_server_wait(srv, t).edges == dg.solve(s).edges
+        with pytest.raises(st.SteinerError) as e:
+            st.steiner_server_wait(srv, 987654321)
+        assert e.value.code == st.EINVAL
+    finally:
+        st.steiner_server_destroy(srv)
+    with pytest.raises(st.SteinerError):
+        st.steiner_server_create(dg.handle, 10, 4)
+
+
+def test_server_disconnected_query(graph):
+    g, cand, dg = graph
+    comp = W.components(g)
+    other = np.nonzero(comp != comp[cand[0]])[0]
+    srv = st.steiner_server_create(dg.handle, 2 << 30, 4)
+    try:
+        t = st.steiner_server_submit(srv, [int(cand[0]), int(other[0])])
+        with pytest.raises(st.SteinerError) as e:
+            st.steiner_server_wait(srv, t)
+        assert e.value.code == st.EDISCONNECTED
+        t = st.steiner_server_submit(srv, cand[:10])
+        assert st.steiner_server_wait(srv, t).edges == O.solve(g, cand[:10]).edges
+    finally:
+        st.steiner_server_destroy(srv)
