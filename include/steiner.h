@@ -20,7 +20,9 @@
  *    accepted and never used; parallel edges are accepted.  nnz must be below
  *    2^32 because an edge is identified by its CSR offset.
  *  - Seeds are vertex ids < n; duplicates are ignored.  Seed index i is the
- *    rank of a seed in the sorted, deduplicated seed list.
+ *    rank of a seed in the sorted, deduplicated seed list.  A query holds at
+ *    most STEINER_MAX_SEEDS distinct seeds, so that the k(k-1)/2 cell pairs
+ *    of G'1 have 32-bit indices.
  *  - Results are exact and unique under these tie rules (the paper leaves
  *    ties open): a vertex joins the cell minimising (distance, seed index);
  *    pred(v) is the smallest in-cell neighbour on a shortest path (then the
@@ -56,6 +58,8 @@ enum {
     STEINER_ECANCELED = -7      /* the server was destroyed before the request finished */
 };
 
+#define STEINER_MAX_SEEDS 92682u
+
 typedef struct steiner_graph steiner_graph;   /* device-resident CSR; owned by the library */
 typedef struct steiner_result steiner_result; /* host arrays of one tree; freed by steiner_result_free */
 typedef struct steiner_server steiner_server; /* continuous-batching query server over one graph */
@@ -77,6 +81,9 @@ typedef struct steiner_options {
 #define STEINER_FLAG_TIMING 1u   /* record per-phase device times (adds synchronisation) */
 #define STEINER_FLAG_COUNTERS 2u /* count relaxation events on the device (the analogue of the
                                     paper's per-phase message counts, Fig. 6) */
+#define STEINER_FLAG_SPLIT 4u    /* within a bucket relax edges of weight <= delta first and the
+                                    heavier ones once per settled vertex (Delta-stepping's
+                                    light/heavy split); no effect with an unbounded bucket */
 
 /* Per-solve statistics (filled for steiner_solve / steiner_solve_batch results). */
 typedef struct steiner_stats {

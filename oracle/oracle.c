@@ -166,7 +166,7 @@ int oracle_voronoi(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, con
     return ORACLE_OK;
 }
 
-/* pred(v) for every vertex (Alg. 4 line "pred(v_j) <- v_p", made canonical):
+/* pred(v) for every vertex (the predecessor Alg. 4 records while relaxing, made canonical):
  * seeds point to themselves, unreached vertices to IDX_NONE, any other v to
  * the first entry of row v (smallest neighbour, then smallest offset) that is
  * in the same cell and lies on a shortest path: dist[u] + w == dist[v]. */

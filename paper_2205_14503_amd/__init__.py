@@ -29,6 +29,8 @@ CODE_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDISCONNECTED: "EDIS
               EOVERFLOW: "EOVERFLOW", EDEVICE: "EDEVICE", ETIMEDOUT: "ETIMEDOUT", ECANCELED: "ECANCELED"}
 FLAG_TIMING = 1
 FLAG_COUNTERS = 2
+FLAG_SPLIT = 4
+MAX_SEEDS = 92682
 DRIVER_DEFAULT, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
 
 EXPORTS = [

@@ -11,12 +11,19 @@ constexpr uint32_t DIST_INF = 0xFFFFFFFFu;   // unreached distance (also the sat
 constexpr uint32_t NONE = 0xFFFFFFFFu;       // no vertex / no predecessor
 constexpr uint32_t MAX_SLOTS = 4096;         // queries resident in one pass (12-bit slot field)
 
-// Near-frontier item encodings.
-//  S item: (slot << 32) | v                    -- a row of degree <= small_max
-//  B item: (slot << 52) | (chunk << 32) | v    -- `chunk`-th piece of a larger row
-__host__ __device__ inline uint64_t s_item(uint32_t slot, uint32_t v) { return ((uint64_t)slot << 32) | v; }
-__host__ __device__ inline uint64_t b_item(uint32_t slot, uint32_t chunk, uint32_t v) {
-    return ((uint64_t)slot << 52) | ((uint64_t)chunk << 32) | v;
+// Frontier item encodings.  A light item relaxes the row's light edges
+// (w <= delta) of a vertex inside its bucket; a heavy item (flag set) relaxes
+// the heavy edges (w > delta) of a vertex whose bucket has closed.
+//  S item: (heavy << 63) | (slot << 32) | v                  -- row of degree <= small_max
+//  B item: (slot << 52) | (heavy << 51) | (chunk << 32) | v  -- chunk < 2^19 of a larger row
+constexpr uint32_t CHUNK_BITS = 19;
+__host__ __device__ inline uint64_t s_item(uint32_t slot, uint32_t v, bool heavy = false) {
+    return ((uint64_t)heavy << 63) | ((uint64_t)slot << 32) | v;
+}
+__host__ __device__ inline uint32_t s_slot(uint64_t it) { return (uint32_t)(it >> 32) & 0xFFFu; }
+__host__ __device__ inline bool s_heavy(uint64_t it) { return (it >> 63) != 0; }
+__host__ __device__ inline uint64_t b_item(uint32_t slot, uint32_t chunk, uint32_t v, bool heavy = false) {
+    return ((uint64_t)slot << 52) | ((uint64_t)heavy << 51) | ((uint64_t)chunk << 32) | v;
 }
 
 // Per-query control, stored structure-of-arrays so the persistent kernel can
@@ -89,6 +96,8 @@ struct VorParams {
     Counters *cnt;
     uint32_t *far_min;   // [3][slots]: min dist parked in round r (rotating)
     uint32_t *near_mark; // [3][slots]: 1 if the query pushed near items in round r (rotating)
+    uint32_t *settle_mark; // [3][slots]: 1 if the query expanded a vertex in round r whose heavy edges wait
+    uint8_t *settled;    // [slots * n]: vertex expanded in its query's open bucket, heavy edges pending
     SlotArrays slot;     // [slots] each
     PassCtl *pass;
     uint32_t nslots;     // allocated slots
@@ -97,6 +106,7 @@ struct VorParams {
     uint32_t chunk;
     uint32_t local_iters; // batches of the wave-local queue expanded per unit (0 = no local queue)
     uint32_t counting;    // 1: accumulate Counters::ev
+    uint32_t split;       // 1: light/heavy edge split (finite delta)
 };
 
 enum : uint32_t {

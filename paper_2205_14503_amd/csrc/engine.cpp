@@ -121,6 +121,7 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
     r.local_iters = g->tuned_local ? (g->tuned_local == 0xFFFFFFFFu ? 0 : g->tuned_local) : 8;
     r.timing = false;
     r.counting = false;
+    r.split = g->tuned_split != 0;
     if (const char *s = getenv("STEINER_DRIVER")) r.driver = (uint32_t)atoi(s);
     if (const char *s = getenv("STEINER_LOCAL")) r.local_iters = (uint32_t)strtoul(s, nullptr, 10);
     if (const char *s = getenv("STEINER_DELTA")) r.delta = (uint32_t)strtoul(s, nullptr, 10);
@@ -134,12 +135,17 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
         if (o->local_iters) r.local_iters = o->local_iters == 0xFFFFFFFFu ? 0 : o->local_iters;
         r.timing = (o->flags & STEINER_FLAG_TIMING) != 0;
         r.counting = (o->flags & STEINER_FLAG_COUNTERS) != 0;
+        if (o->flags & STEINER_FLAG_SPLIT) r.split = true;
     }
     if (r.delta == 0) r.delta = 1;
     if (r.block < 64 || r.block > 1024 || r.block % 64) r.block = 256;
     if (r.block > 256) r.block = 256;  // per-wave LDS scratch of the relaxation kernels (~10 KB per wave)
     if (r.chunk < 64) r.chunk = 64;
-    if (r.grid == 0) r.grid = (uint32_t)std::max(1, g->cu_count) * 2u * (r.driver == 2 ? 1024u / r.block : 1u);
+    while ((g->max_deg + r.chunk - 1) / r.chunk >= (1ull << CHUNK_BITS)) r.chunk *= 2;  // chunk index field
+    // host-stepped: five 256-thread workgroups per CU, the occupancy the relaxation kernel's registers allow;
+    // persistent: two per CU at most, the co-residency its grid barrier needs
+    if (r.grid == 0)
+        r.grid = (uint32_t)std::max(1, g->cu_count) * (r.driver == 2 ? 2u * (1024u / r.block) : 5u * (256u / r.block));
     return r;
 }
 
@@ -152,50 +158,6 @@ void pair_from_index(uint64_t p, uint32_t *i, uint32_t *j) {
     while ((jj + 1) * jj / 2 <= p) jj++;
     *j = (uint32_t)jj;
     *i = (uint32_t)(p - jj * (jj - 1) / 2);
-}
-
-// MST of G'1 by Prim's algorithm under the strict order (d'1, i, j); the
-// order is total, so the tree is the unique one any correct MST code returns.
-// Returns the chosen list positions, or EDISCONNECTED.
-int prim_mst(uint32_t k, const std::vector<uint32_t> &pidx, const std::vector<uint64_t> &pval,
-             std::vector<uint32_t> &chosen) {
-    const size_t m = pidx.size();
-    std::vector<uint32_t> pi(m), pj(m);
-    std::vector<uint32_t> deg(k + 1, 0);
-    for (size_t t = 0; t < m; t++) {
-        pair_from_index(pidx[t], &pi[t], &pj[t]);
-        deg[pi[t] + 1]++;
-        deg[pj[t] + 1]++;
-    }
-    for (uint32_t v = 0; v < k; v++) deg[v + 1] += deg[v];
-    std::vector<uint32_t> adj(2 * m), fill(deg.begin(), deg.end() - 1);
-    for (size_t t = 0; t < m; t++) {
-        adj[fill[pi[t]]++] = (uint32_t)t;
-        adj[fill[pj[t]]++] = (uint32_t)t;
-    }
-    typedef std::tuple<uint32_t, uint32_t, uint32_t, uint32_t> HE;  // (d'1, i, j, list position)
-    std::priority_queue<HE, std::vector<HE>, std::greater<HE>> pq;
-    std::vector<uint8_t> in(k, 0);
-    chosen.clear();
-    auto add = [&](uint32_t v) {
-        in[v] = 1;
-        for (uint32_t a = deg[v]; a < deg[v + 1]; a++) {
-            uint32_t t = adj[a];
-            uint32_t o = pi[t] == v ? pj[t] : pi[t];
-            if (!in[o]) pq.emplace((uint32_t)(pval[t] >> 32), pi[t], pj[t], t);
-        }
-    };
-    add(0);
-    while (!pq.empty() && chosen.size() + 1 < k) {
-        HE top = pq.top();
-        pq.pop();
-        uint32_t t = std::get<3>(top);
-        uint32_t o = in[pi[t]] ? pj[t] : pi[t];
-        if (in[pi[t]] && in[pj[t]]) continue;
-        chosen.push_back(t);
-        add(o);
-    }
-    return chosen.size() + 1 == k ? STEINER_OK : STEINER_EDISCONNECTED;
 }
 
 }  // namespace stn
@@ -308,6 +270,7 @@ static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t
     hoff.push_back(0);
     for (uint32_t v = 0; v < n; v++) {
         uint64_t d = g->h_rp[v + 1] - g->h_rp[v];
+        g->max_deg = std::max(g->max_deg, d);
         if (d > scan_heavy) {
             hrows.push_back(v);
             hoff.push_back(hoff.back() + (uint32_t)((d + scan_chunk - 1) / scan_chunk));
@@ -333,8 +296,11 @@ static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t
     dg.scan_chunk = scan_chunk;
     const double avg_w = nnz ? (double)wsum / (double)nnz : 1.0;
     const double avg_deg = n ? (double)nnz / (double)n : 1.0;
-    double d = 2.0 * avg_w / std::max(1.0, avg_deg);
-    g->default_delta = (uint32_t)std::max(1.0, std::min(d, 4.0e9));
+    // the classic bucket width (about the mean weight over the mean degree) is one of the tuner's
+    // candidates; untuned solves use one unbounded bucket, which is never far from the best here
+    const double d = 2.0 * avg_w / std::max(1.0, avg_deg);
+    g->classic_delta = (uint32_t)std::max(1.0, std::min(d, 4.0e9));
+    g->default_delta = 0xFFFFFFFFu;
     g->avg_w = avg_w;
     return STEINER_OK;
 }
@@ -466,6 +432,8 @@ int stn::canon_seeds(const steiner_graph *g, const uint32_t *seeds, uint32_t k, 
         if (s >= g->n) return fail(STEINER_EINVAL, "seed %u >= n", s);
     std::sort(S.begin(), S.end());
     S.erase(std::unique(S.begin(), S.end()), S.end());
+    if (S.size() > STEINER_MAX_SEEDS)
+        return fail(STEINER_EINVAL, "%zu distinct seeds; at most %u", S.size(), (unsigned)STEINER_MAX_SEEDS);
     return STEINER_OK;
 }
 
@@ -516,41 +484,46 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
     if ((rc = canon_seeds(g, seeds, k, S))) return rc;
     if (S.size() < 2) return fail(STEINER_EINVAL, "tuning needs at least 2 distinct seeds");
     const double w = std::max(1.0, g->avg_w);
-    std::vector<uint32_t> deltas = {g->default_delta, (uint32_t)std::max(1.0, w / 2), (uint32_t)std::max(1.0, 2 * w),
-                                    (uint32_t)std::max(1.0, 8 * w), 0xFFFFFFFFu};
+    std::vector<uint32_t> deltas = {g->classic_delta, (uint32_t)std::max(1.0, w / 4), (uint32_t)std::max(1.0, w),
+                                    (uint32_t)std::max(1.0, 4 * w), (uint32_t)std::max(1.0, 16 * w), 0xFFFFFFFFu};
     std::sort(deltas.begin(), deltas.end());
     deltas.erase(std::unique(deltas.begin(), deltas.end()), deltas.end());
     const uint32_t locals[] = {2, 8, 32};
     double best = 1e300;
-    uint32_t best_d = g->default_delta, best_l = 8;
+    uint32_t best_d = g->default_delta, best_l = 8, best_split = 0;
     for (uint32_t d : deltas)
-        for (uint32_t l : locals) {
-            Options o = resolve_options(g, nullptr);
-            o.delta = d;
-            o.local_iters = l;
-            double t_min = 1e300;
-            for (int rep = 0; rep < 2; rep++) {
-                std::vector<Query> qs(1);
-                qs[0].S = S;
-                const auto t0 = std::chrono::steady_clock::now();
-                if ((rc = run_pass(g, o, qs))) return rc;
-                const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-                if (qs[0].status && qs[0].status != STEINER_EDISCONNECTED && qs[0].status != STEINER_EOVERFLOW)
-                    return qs[0].status;
-                t_min = std::min(t_min, t);
+        for (uint32_t l : locals)
+            for (uint32_t split = 0; split < (d == 0xFFFFFFFFu ? 1u : 2u); split++) {
+                Options o = resolve_options(g, nullptr);
+                o.delta = d;
+                o.local_iters = l;
+                o.split = split != 0;
+                double t_min = 1e300;
+                for (int rep = 0; rep < 2; rep++) {
+                    std::vector<Query> qs(1);
+                    qs[0].S = S;
+                    const auto t0 = std::chrono::steady_clock::now();
+                    if ((rc = run_pass(g, o, qs))) return rc;
+                    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                    if (qs[0].status && qs[0].status != STEINER_EDISCONNECTED && qs[0].status != STEINER_EOVERFLOW)
+                        return qs[0].status;
+                    t_min = std::min(t_min, t);
+                }
+                if (t_min < best) {
+                    best = t_min;
+                    best_d = d;
+                    best_l = l;
+                    best_split = split;
+                }
             }
-            if (t_min < best) {
-                best = t_min;
-                best_d = d;
-                best_l = l;
-            }
-        }
     g->tuned_delta = best_d;
     g->tuned_local = best_l;
+    g->tuned_split = best_split;
     if (out) {
         memset(out, 0, sizeof(*out));
         out->delta = best_d;
         out->local_iters = best_l;
+        out->flags = best_split ? STEINER_FLAG_SPLIT : 0u;
     }
     return STEINER_OK;
 }

@@ -37,19 +37,32 @@ struct HostPinned {
 
 struct Options {
     uint32_t delta, driver, block, grid, small_max, chunk, local_iters;
-    bool timing, counting;
+    bool timing, counting, split;
+};
+
+// Device buffers of Alg. 2 Steps 3-7 for one query at a time: the MST's
+// lists and per-seed arrays, the expansion's vertex marks (kept all zero
+// between calls) and its output edges.
+struct TailScratch {
+    DevBuf mst, mark, out;
+    HostPinned host;
+    uint32_t mark_n = 0;  // mark holds this many zero bytes
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    int prepare(uint32_t n, uint32_t k, uint64_t m, hipStream_t st);
+    void release();
 };
 
 // Device workspace of a multi-query pass, reused across solves of a graph.
 struct Workspace {
-    DevBuf key, aux, dirty, items_s[2], items_b[2], ctl, heavy_pe, seeds, pt, cidx, cval, ptrs, visited, oedges,
-        sel;
+    DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, seeds, pt, cidx, cval, ptrs;
     HostPinned host;
+    TailScratch tail;
     void release() {
-        DevBuf *all[] = {&key, &aux, &dirty, &items_s[0], &items_s[1], &items_b[0], &items_b[1], &ctl, &heavy_pe,
-                         &seeds, &pt, &cidx, &cval, &ptrs, &visited, &oedges, &sel};
+        DevBuf *all[] = {&key, &aux, &dirty, &settled, &items_s[0], &items_s[1], &items_b[0], &items_b[1], &ctl, &heavy_pe,
+                         &seeds, &pt, &cidx, &cval, &ptrs};
         for (DevBuf *b : all) b->release();
         host.release();
+        tail.release();
     }
 };
 
@@ -58,7 +71,8 @@ enum StopAfter { STOP_NEVER = 0, STOP_AFTER_SCAN = 1, STOP_AFTER_COMPACT = 2 };
 // Offsets of the per-pass control region (counters, pass control, per-slot
 // arrays) for Q slots; every array starts on a 256-byte boundary.
 struct Layout {
-    size_t counters, pass, thr, thr_prev, pt_ptr, pt_len, oidx_ptr, oval_ptr, ocap, far_min, near_mark, carry, active,
+    size_t counters, pass, thr, thr_prev, pt_ptr, pt_len, oidx_ptr, oval_ptr, ocap, far_min, near_mark, settle_mark,
+        carry, active,
         adv, done, advances, slot_err, out_cnt, slot_ids, total;
     explicit Layout(uint32_t Q) {
         size_t o = 0;
@@ -78,6 +92,7 @@ struct Layout {
         ocap = take(8ull * Q);
         far_min = take(12ull * Q);
         near_mark = take(12ull * Q);
+        settle_mark = take(12ull * Q);
         carry = take(4ull * Q);
         active = take(4ull * Q);
         adv = take(4ull * Q);
@@ -112,11 +127,14 @@ struct steiner_graph {
     uint2 *d_adj = nullptr;
     uint32_t *d_heavy_rows = nullptr, *d_heavy_off = nullptr;
     uint32_t nheavy = 0;
+    uint64_t max_deg = 0;
     stn::DevGraph dg{};
     std::vector<uint64_t> h_rp;  // host copy of the row offsets
-    uint32_t default_delta = 1;
+    uint32_t default_delta = 0xFFFFFFFFu;
+    uint32_t classic_delta = 1;
     uint32_t tuned_delta = 0;    // set by steiner_graph_tune
     uint32_t tuned_local = 0;
+    uint32_t tuned_split = 0;
     double avg_w = 1.0;
     int cu_count = 256;
     std::mutex mu;               // serialises solves on this graph
@@ -134,22 +152,23 @@ struct Query {
     uint64_t *want_key = nullptr;
     uint32_t *want_pred = nullptr;
     int stop_after = STOP_NEVER;
-    std::vector<uint32_t> pidx;  // G'1 entries (lower-triangular pair index)
+    std::vector<uint32_t> pidx;  // G'1 entries (lower-triangular pair index), STOP_AFTER_COMPACT only
     std::vector<uint64_t> pval;  // (d'1 << 32) | edge id
 };
 
 Options resolve_options(const steiner_graph *g, const steiner_options *o);
 int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs);
-// Steps 3-7 of one query whose G'1 entries (pidx, pval) are on the host and
-// whose keys / preds are on the device: MST, pruning, expansion, D.
+// Steps 3-7 of one query, on the device: MST of its G'1 (m compacted pair
+// indices g1_idx into its pair table pt), the kept cross-cell edges, the pred
+// walks and D.  key / pred are the query's slot arrays.  The tree's edges come
+// back sorted by (a, b, w); EDISCONNECTED if the MST has fewer than k-1 edges.
 int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, const uint32_t *pred, uint32_t k,
-                 const std::vector<uint32_t> &pidx, const std::vector<uint64_t> &pval, DevBuf &sel_buf,
-                 uint32_t *visited, uint32_t *oedges, std::unique_ptr<steiner_result> &out, double *ms_mst,
-                 double *ms_expand);
-int prim_mst(uint32_t k, const std::vector<uint32_t> &pidx, const std::vector<uint64_t> &pval,
-             std::vector<uint32_t> &chosen);
+                 const uint64_t *pt, const uint32_t *g1_idx, uint32_t m, TailScratch &ts,
+                 std::unique_ptr<steiner_result> &out, double *ms_mst, double *ms_expand);
 void pair_from_index(uint64_t p, uint32_t *i, uint32_t *j);
 int canon_seeds(const steiner_graph *g, const uint32_t *seeds, uint32_t k, std::vector<uint32_t> &S);
 uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chunk);
+// Fills the pass parameters shared by every driver for Q slots.
+void bind_state(VorParams &P, const Options &o, uint64_t cap_s, uint64_t cap_b);
 
 }  // namespace stn

@@ -31,11 +31,12 @@ struct ExpandParams {
     DevGraph g;
     const uint64_t *key;     // slot base
     const uint32_t *pred;    // slot base
-    const uint32_t *sel_e;   // chosen cross-cell edge ids
-    uint32_t nsel;
-    uint32_t *visited;       // bitmap, n bits, zeroed
-    uint32_t *oa, *ob, *ow;  // outputs, capacity n
-    uint32_t *ocnt;
+    const uint32_t *sel_e;   // chosen cross-cell edge ids (CSR offsets)
+    const uint32_t *nsel;    // their number (device)
+    uint32_t nsel_max;       // upper bound of *nsel, sizes the launch
+    uint32_t *mark;          // n bytes (rounded up to 4), all zero on entry and again on exit
+    uint32_t *oa, *ob, *ow;  // output edges, capacity n
+    uint32_t *ocnt;          // output count, zero on entry
 };
 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t count, uint64_t value, hipStream_t s);
@@ -57,6 +58,23 @@ int persistent_max_grid(uint32_t block);
 
 hipError_t launch_scan(const ScanParams &S, uint32_t grid, uint32_t block, hipStream_t s);
 hipError_t launch_compact(const CompactParams &C, uint32_t grid, uint32_t block, hipStream_t s);
-hipError_t launch_expand(const ExpandParams &E, hipStream_t s);
+hipError_t launch_expand(const ExpandParams &E, uint32_t emit_grid, hipStream_t s);
+
+// Borůvka MST of one query's G'1 on the device (Alg. 2 Step 3).  The edge
+// order is the strict (d'1, i, j): key = (d'1 << 32) | rank(i, j) with the
+// row-major rank of the pair among all i < j, which fits in 32 bits while
+// k(k-1)/2 does; so the tree is the one Kruskal or Prim under that order
+// returns.  Scratch for m G'1 entries and k seeds, see MstParams.
+struct MstParams {
+    const uint64_t *pt;       // the query's pair table: (d'1 << 32) | edge id, index j(j-1)/2 + i
+    uint32_t k;
+    uint32_t *edges[2];       // [m] each: ping-pong lists of pair indices that still join two components
+    uint32_t *hdr;            // [4]: edge counts of the two lists, chosen-edge count, expansion output count
+    uint32_t *par;            // [k] component root of each seed
+    uint32_t *hook;           // [k] parent of each root after the current round's hooking
+    unsigned long long *best; // [k] lightest key leaving each root
+    uint32_t *sel;            // [k] chosen cross-cell edge ids (CSR offsets), hdr[2] of them
+};
+hipError_t launch_mst(const MstParams &M, const uint32_t *g1_idx, uint32_t m, hipStream_t s);
 
 }  // namespace stn

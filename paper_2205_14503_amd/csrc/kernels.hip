@@ -18,6 +18,8 @@
 //
 // Step 2 (Alg. 5) and the canonical predecessor share one streaming pass over
 // the CSR: every entry gathers its neighbour's key once.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace stn {
@@ -88,7 +90,7 @@ DEVI void append_s(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, 
 
 // Wave-aggregated append of the chunks of rows larger than small_max.
 DEVI void append_b(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, uint32_t slot, uint32_t v,
-                   uint32_t deg) {
+                   uint32_t deg, bool heavy = false) {
     uint64_t m = __ballot(pred);
     if (m == 0) return;
     uint32_t nch = pred ? (deg + P.chunk - 1) / P.chunk : 0;
@@ -101,7 +103,7 @@ DEVI void append_b(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, 
         uint32_t pos = base + incl - nch;
         for (uint32_t c = 0; c < nch; c++) {
             if (pos + c < P.cap_b) {
-                P.items_b[list][pos + c] = b_item(slot, c, v);
+                P.items_b[list][pos + c] = b_item(slot, c, v, heavy);
             } else {
                 atomicOr(&P.pass->err, ERR_LIST_OVERFLOW);
                 break;
@@ -114,8 +116,8 @@ DEVI void append_b(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, 
 // itself within the same round, so one round advances many hops along
 // long shortest paths (high-diameter graphs otherwise need a global round per
 // hop).  Anything the queue cannot hold goes to the next round's list.
-constexpr uint32_t LQ_CAP = 256;
-constexpr uint32_t OUT_CAP = 256;
+constexpr uint32_t LQ_CAP = 128;
+constexpr uint32_t OUT_CAP = 128;
 
 struct WaveScratch {
     uint32_t incl[64];
@@ -268,21 +270,27 @@ DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr
 // with key kv in query `slot` (deg = 0 for idle lanes), 64 * UNROLL edges per
 // step, balanced across the wave by a prefix sum of the degrees (coalesced
 // 8-byte (col, w) loads within each row).
-DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t slot, uint64_t kv,
-                       uint32_t beg, uint32_t deg, WaveScratch *L, bool use_lq, uint32_t &lq_head,
-                       uint32_t &lq_tail) {
+DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t slot, uint32_t v,
+                       uint64_t kv, uint32_t beg, uint32_t deg, bool heavy, WaveScratch *L, bool use_lq,
+                       uint32_t &lq_head, uint32_t &lq_tail) {
     const uint32_t ln = lane();
     count(P, L, EV_ITEMS, kv != KEY_INF);
+    if (P.split && !heavy && kv != KEY_INF) {  // its heavy edges wait until the bucket closes
+        P.settled[(size_t)slot * P.g.n + v] = 1;
+        uint32_t *sm = P.settle_mark + (size_t)R.b * P.nslots + slot;
+        if (*sm == 0) *sm = 1;
+    }
     const uint32_t incl = wave_incl_scan(deg);
     const uint32_t total = __shfl(incl, 63, 64);
     wave_sync();
     L->incl[ln] = incl;
     L->beg[ln] = beg;
     L->slot[ln] = slot;
+    L->pad[ln] = heavy ? 1u : 0u;
     L->key[ln] = kv;
     wave_sync();
     for (uint32_t base = 0; base < total; base += 64 * UNROLL) {
-        bool valid[UNROLL];
+        bool valid[UNROLL], hv[UNROLL];
         uint32_t sl[UNROLL], uu[UNROLL], ww[UNROLL], e[UNROLL];
         uint64_t ks[UNROLL];
 #pragma unroll
@@ -302,12 +310,14 @@ DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *th
             e[i] = L->beg[j] + (t - ex);
             sl[i] = L->slot[j];
             ks[i] = L->key[j];
+            hv[i] = L->pad[j] != 0;
         }
 #pragma unroll
         for (int i = 0; i < UNROLL; i++) {
             const uint2 a = valid[i] ? P.g.adj[e[i]] : make_uint2(0, 0);
             uu[i] = a.x;
             ww[i] = a.y;
+            if (P.split) valid[i] = valid[i] && (hv[i] ? a.y > P.delta : a.y <= P.delta);
         }
         relax_multi(P, R, thr, valid, sl, ks, uu, ww, L, use_lq, lq_head, lq_tail);
     }
@@ -318,9 +328,17 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
                           bool use_lq, uint32_t &lq_head, uint32_t &lq_tail) {
     const uint64_t it = P.items_b[R.cur][idx];
     const uint32_t slot = (uint32_t)(it >> 52);
-    const uint32_t c = (uint32_t)(it >> 32) & 0xFFFFFu;
+    const bool heavy = ((it >> 51) & 1u) != 0;
+    const uint32_t c = (uint32_t)(it >> 32) & ((1u << CHUNK_BITS) - 1);
     const uint32_t v = (uint32_t)it;
     const uint64_t kv = ld_agent(P.key + (size_t)slot * P.g.n + v);
+    if (P.split && !heavy && c == 0 && kv != KEY_INF) {  // heavy edges wait until the bucket closes
+        if (lane() == 0) {
+            P.settled[(size_t)slot * P.g.n + v] = 1;
+            uint32_t *sm = P.settle_mark + (size_t)R.b * P.nslots + slot;
+            if (*sm == 0) *sm = 1;
+        }
+    }
     const uint32_t beg = P.g.rp[v] + c * P.chunk;
     const uint32_t lim = P.g.rp[v + 1];
     uint32_t end = (lim - beg > P.chunk) ? beg + P.chunk : lim;
@@ -336,6 +354,7 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
             const uint2 a = valid[i] ? P.g.adj[e] : make_uint2(0, 0);
             uu[i] = a.x;
             ww[i] = a.y;
+            if (P.split) valid[i] = valid[i] && (heavy ? a.y > P.delta : a.y <= P.delta);
             sl[i] = slot;
             ks[i] = kv;
         }
@@ -359,7 +378,7 @@ DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr
         const uint32_t beg = has ? L->lq_beg[at] : 0;
         const uint32_t deg = has ? L->lq_deg[at] : 0;
         h += take;
-        expand_items(P, R, thr, (uint32_t)(item >> 32), kv, beg, deg, L, true, h, t);
+        expand_items(P, R, thr, s_slot(item), (uint32_t)item, kv, beg, deg, false, L, true, h, t);
     }
     while (h != t) {
         const uint32_t take = min(t - h, 64u);
@@ -369,7 +388,7 @@ DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr
         h += take;
         bool claim = false;
         if (has) {
-            const uint32_t slot = (uint32_t)(item >> 32), v = (uint32_t)item;
+            const uint32_t slot = s_slot(item), v = (uint32_t)item;
             if (atomicExch(P.aux + (size_t)slot * P.g.n + v, R.r + 1) != R.r + 1) {
                 claim = true;
                 uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + slot;
@@ -394,17 +413,19 @@ DEVI void relax_round_body(const VorParams &P, const RoundIdx &R, const uint64_t
         uint32_t h = 0, t = 0;
         if (u < ng) {
             const uint32_t idx = u * 64 + lane();
-            uint32_t slot = 0, beg = 0, deg = 0;
+            uint32_t slot = 0, beg = 0, deg = 0, v = 0;
             uint64_t kv = KEY_INF;
+            bool heavy = false;
             if (idx < cs) {
                 const uint64_t it = P.items_s[R.cur][idx];
-                slot = (uint32_t)(it >> 32);
-                const uint32_t v = (uint32_t)it;
+                slot = s_slot(it);
+                heavy = s_heavy(it);
+                v = (uint32_t)it;
                 kv = ld_agent(P.key + (size_t)slot * P.g.n + v);
                 beg = P.g.rp[v];
                 deg = kv == KEY_INF ? 0 : P.g.rp[v + 1] - beg;
             }
-            expand_items(P, R, thr, slot, kv, beg, deg, L, use_lq, h, t);
+            expand_items(P, R, thr, slot, v, kv, beg, deg, heavy, L, use_lq, h, t);
         } else {
             process_b_chunk(P, R, thr, u - ng, L, use_lq, h, t);
         }
@@ -428,6 +449,8 @@ DEVI void decide_slot(const VorParams &P, uint32_t r, uint32_t q, uint64_t *thr,
     if (!active[q]) return;
     const uint32_t b = r % 3u;
     uint32_t c = min(carry[q], ld_agent(P.far_min + (size_t)b * P.nslots + q));
+    // vertices expanded in the open bucket still owe their heavy edges: work at >= thr
+    if (ld_agent(P.settle_mark + (size_t)b * P.nslots + q)) c = min(c, (uint32_t)min(thr[q], (uint64_t)DIST_INF - 1));
     const bool has_near = ld_agent(P.near_mark + (size_t)b * P.nslots + q) != 0;
     if (!has_near) {
         if (c == DIST_INF) {
@@ -453,7 +476,13 @@ DEVI void decide_slot(const VorParams &P, uint32_t r, uint32_t q, uint64_t *thr,
 // the query's near mark in that buffer is set when something was pushed.
 DEVI void advance_body(const VorParams &P, const uint64_t *thr, const uint64_t *thr_prev, const uint32_t *adv,
                        uint32_t stamp, uint32_t list, uint32_t cidx, uint32_t fm_buf, int nm_buf, uint32_t wave_gid,
-                       uint32_t nwaves) {
+                       uint32_t nwaves, WaveScratch *L) {
+    // S items go through the wave's staging buffer (one list atomic per flush)
+    RoundIdx Rs;
+    Rs.nxt = list;
+    Rs.c_nxt = cidx;
+    if (lane() == 0) L->out_n = 0;
+    wave_sync();
     const uint32_t n = P.g.n;
     for (uint32_t q = 0; q < P.nslots; q++) {
         if (!adv[q]) continue;
@@ -462,11 +491,15 @@ DEVI void advance_body(const VorParams &P, const uint64_t *thr, const uint64_t *
         bool pushed = false;
         for (uint32_t base = wave_gid * 64; base < n; base += nwaves * 64) {
             const uint32_t v = base + lane();
-            bool push = false;
+            bool push = false, hpush = false;
             uint32_t deg = 0;
             if (v < n) {
                 const size_t o = (size_t)q * n + v;
-                if (P.dirty[o]) {
+                if (P.split && P.settled[o]) {  // the closed bucket's vertices relax their heavy edges
+                    P.settled[o] = 0;
+                    deg = P.g.rp[v + 1] - P.g.rp[v];
+                    hpush = true;
+                } else if (P.dirty[o]) {
                     const uint32_t d = (uint32_t)(ld_agent(P.key + o) >> 32);
                     if (d < lo) {
                         P.dirty[o] = 0;
@@ -480,10 +513,11 @@ DEVI void advance_body(const VorParams &P, const uint64_t *thr, const uint64_t *
                     }
                 }
             }
-            pushed |= __ballot(push) != 0;
-            append_s(P, list, cidx, push && deg <= P.small_max, s_item(q, v));
-            append_b(P, list, cidx, push && deg > P.small_max, q, v, deg);
+            pushed |= __ballot(push || hpush) != 0;
+            stage_s(P, Rs, L, (push || hpush) && deg <= P.small_max, s_item(q, v, hpush));
+            append_b(P, list, cidx, (push || hpush) && deg > P.small_max, q, v, deg, hpush);
         }
+        flush_out(P, Rs, L);
         kept = wave_min(kept);
         if (lane() == 0) {
             if (kept != DIST_INF) atomicMin(P.far_min + (size_t)fm_buf * P.nslots + q, kept);
@@ -508,7 +542,7 @@ __global__ void __launch_bounds__(1024) k_round(VorParams P) {
     const uint32_t wave_gid = blockIdx.x * wpb + w, nwaves = gridDim.x * wpb;
     if (ld_agent(&P.pass->any_adv))
         advance_body(P, P.slot.thr, P.slot.thr_prev, P.slot.adv, r + 1, R.nxt, R.c_nxt, R.b, (int)R.b, wave_gid,
-                     nwaves);
+                     nwaves, &s_wave[w]);
     const uint32_t cs = min(ld_agent(&P.cnt->s[r % 3u]), P.cap_s), cb = min(ld_agent(&P.cnt->b[r % 3u]), P.cap_b);
     relax_round_body(P, R, P.slot.thr, cs, cb, &s_wave[w], wave_gid, nwaves);
 
@@ -528,6 +562,7 @@ __global__ void __launch_bounds__(1024) k_round(VorParams P) {
         decide_slot(P, r, q, P.slot.thr, P.slot.thr_prev, P.slot.carry, P.slot.active, P.slot.adv, P.slot.done,
                     P.slot.advances, aa, act);
         P.near_mark[(size_t)nb * P.nslots + q] = 0;
+        P.settle_mark[(size_t)nb * P.nslots + q] = 0;
         P.far_min[(size_t)nb * P.nslots + q] = DIST_INF;
     }
     if (aa) atomicOr(&s_adv, 1);
@@ -611,6 +646,7 @@ __global__ void __launch_bounds__(1024) k_persistent(VorParams P, uint32_t max_r
             const uint32_t nb = (r + 1) % 3u;
             for (uint32_t q = threadIdx.x; q < ns; q += blockDim.x) {
                 P.near_mark[(size_t)nb * ns + q] = 0;
+                P.settle_mark[(size_t)nb * ns + q] = 0;
                 P.far_min[(size_t)nb * ns + q] = DIST_INF;
             }
             if (threadIdx.x == 0) {
@@ -630,7 +666,7 @@ __global__ void __launch_bounds__(1024) k_persistent(VorParams P, uint32_t max_r
         const bool any_adv = s_any_adv != 0, any_act = s_any_act != 0;
         if (any_adv) {
             advance_body(P, s_thr, s_thr_prev, s_adv, r + 1, (r + 1) & 1u, (r + 1) % 3u, (r + 1) % 3u, -1, wave_gid,
-                         nwaves);
+                         nwaves, &s_wave[w]);
             if (!(ok = grid_barrier(P.cnt, gridDim.x, P.pass, &s_abort))) break;
         }
         r++;
@@ -683,6 +719,7 @@ __global__ void k_pass_reset(VorParams P) {
         for (int b = 0; b < 3; b++) {
             P.far_min[(size_t)b * P.nslots + q] = DIST_INF;
             P.near_mark[(size_t)b * P.nslots + q] = 0;
+            P.settle_mark[(size_t)b * P.nslots + q] = 0;
         }
         P.slot.active[q] = 0;
         P.slot.done[q] = 0;
@@ -695,12 +732,13 @@ __global__ void k_pass_reset(VorParams P) {
 }
 
 // Per-vertex state of one query: keys unreached, stamps and marks clear.
-__global__ void k_slot_clear(uint64_t *key, uint32_t *aux, uint8_t *dirty, uint32_t n, uint32_t *heavy_pe,
-                             uint32_t nheavy) {
+__global__ void k_slot_clear(uint64_t *key, uint32_t *aux, uint8_t *dirty, uint8_t *settled, uint32_t n,
+                             uint32_t *heavy_pe, uint32_t nheavy) {
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         key[v] = KEY_INF;
         aux[v] = 0;
         dirty[v] = 0;
+        settled[v] = 0;
     }
     for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < nheavy; h += gridDim.x * blockDim.x)
         heavy_pe[h] = NONE;
@@ -741,6 +779,7 @@ __global__ void k_slot_seed(VorParams P, uint32_t slot, const uint32_t *seeds, u
         for (int b = 0; b < 3; b++) {
             P.far_min[(size_t)b * P.nslots + slot] = DIST_INF;
             P.near_mark[(size_t)b * P.nslots + slot] = 0;
+            P.settle_mark[(size_t)b * P.nslots + slot] = 0;
         }
         P.pass->all_done = 0;
     }
@@ -956,43 +995,196 @@ __global__ void __launch_bounds__(256) k_compact(CompactParams C) {
 
 // --------------------------------------------------------------- expansion
 
-DEVI void emit_edge(const ExpandParams &E, uint32_t x, uint32_t y, uint32_t w) {
-    const uint32_t pos = atomicAdd(E.ocnt, 1u);
-    if (pos < E.g.n) {
+// Alg. 2 Steps 5-6 on the pred forest: the tree is every chosen cross-cell
+// edge plus, from both of its endpoints, every edge (x, pred(x)) up to the
+// cell's seed.  Walks only mark the vertices they pass (one dependent load
+// per step, no read-back); one pass over the marks then writes each marked
+// vertex's edge once, which is the set semantics of E_S, and clears the mark.
+
+DEVI void emit_edges(const ExpandParams &E, bool on, uint32_t x, uint32_t y, uint32_t w) {
+    const uint64_t m = __ballot(on);
+    if (!m) return;
+    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1;
+    uint32_t pos = 0;
+    if (lane() == leader) pos = atomicAdd(E.ocnt, (uint32_t)__popcll(m));
+    pos = __shfl(pos, leader, 64) + lanes_below(m);
+    if (on && pos < E.g.n) {
         E.oa[pos] = min(x, y);
         E.ob[pos] = max(x, y);
         E.ow[pos] = w;
     }
 }
 
-// Alg. 6: every kept cross-cell edge plus the predecessor paths of both its
-// endpoints up to their seeds; a visited bit makes each path edge appear once.
-__global__ void k_expand(ExpandParams E) {
+// Two threads per chosen edge: thread 2q finds the row u of edge e (binary
+// search over rp), writes (u, v, w) and walks from u; thread 2q+1 walks from v.
+__global__ void __launch_bounds__(256) k_expand_walk(ExpandParams E) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= E.nsel) return;
-    const uint32_t e = E.sel_e[t];
-    uint32_t lo = 0, hi = E.g.n;  // rp[lo] <= e < rp[hi]
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (E.g.rp[mid] <= e) lo = mid; else hi = mid;
-    }
-    const uint2 a = E.g.adj[e];
-    emit_edge(E, lo, a.x, a.y);
-    uint32_t ends[2] = {lo, a.x};
-    for (int s = 0; s < 2; s++) {
-        uint32_t x = ends[s];
-        for (uint32_t steps = 0; steps < E.g.n; steps++) {
-            const uint64_t kx = E.key[x];
-            if ((kx >> 32) == 0) break;  // reached the seed
-            const uint32_t bit = 1u << (x & 31);
-            if (atomicOr(E.visited + (x >> 5), bit) & bit) break;  // another walk owns the rest
-            const uint32_t p = E.pred[x];
-            if (p >= E.g.n) break;  // cannot happen for a converged pass; keeps the walk in bounds
-            const uint64_t kp = E.key[p];
-            emit_edge(E, x, p, (uint32_t)((kx >> 32) - (kp >> 32)));
-            x = p;
+    const uint32_t q = t >> 1, end = t & 1u, n = E.g.n;
+    const bool live = q < *E.nsel;
+    uint32_t x = 0, v = 0, w = 0;
+    if (live) {
+        const uint32_t e = E.sel_e[q];
+        const uint2 a = E.g.adj[e];
+        v = a.x;
+        w = a.y;
+        x = a.x;
+        if (end == 0) {
+            uint32_t lo = 0, hi = n;  // rp[lo] <= e < rp[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (E.g.rp[mid] <= e) lo = mid; else hi = mid;
+            }
+            x = lo;
         }
     }
+    emit_edges(E, live && end == 0, x, v, w);
+    if (!live) return;
+    for (uint32_t steps = 0; steps < n; steps++) {
+        const uint32_t p = E.pred[x];
+        if (p == x || p >= n) break;  // the seed (or, never for a converged pass, an unreached vertex)
+        ((uint8_t *)E.mark)[x] = 1;
+        x = p;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_expand_emit(ExpandParams E) {
+    const uint32_t n = E.g.n, words = (n + 3) / 4;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < words; base += stride) {
+        const uint32_t t = base + threadIdx.x;
+        const uint32_t word = t < words ? E.mark[t] : 0u;
+        if (__ballot(word != 0) == 0) continue;
+        if (word) E.mark[t] = 0u;
+        for (uint32_t b = 0; b < 4; b++) {
+            const uint32_t x = 4 * t + b;
+            const bool on = ((word >> (8 * b)) & 0xFFu) != 0;
+            uint32_t p = 0, w = 0;
+            if (on) {
+                p = E.pred[x];
+                w = (uint32_t)((E.key[x] >> 32) - (E.key[p] >> 32));
+            }
+            emit_edges(E, on, x, p, w);
+        }
+    }
+}
+
+// ------------------------------------------------------------ MST of G'1
+
+DEVI void pair_of(uint32_t p, uint32_t *i, uint32_t *j) {  // inverse of j(j-1)/2 + i, i < j
+    uint32_t jj = (uint32_t)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+    while ((uint64_t)jj * (jj - 1) / 2 > p) jj--;
+    while ((uint64_t)(jj + 1) * jj / 2 <= p) jj++;
+    *j = jj;
+    *i = p - (uint32_t)((uint64_t)jj * (jj - 1) / 2);
+}
+
+// Row-major rank of pair (i, j), i < j < k, among all such pairs, and its inverse.
+DEVI uint64_t row_start(uint64_t i, uint64_t k) { return i * (2 * k - i - 1) / 2; }
+DEVI uint32_t rank_of(uint32_t i, uint32_t j, uint32_t k) { return (uint32_t)(row_start(i, k) + (j - i - 1)); }
+DEVI void rank_pair(uint32_t r, uint32_t k, uint32_t *i, uint32_t *j) {
+    const double a = 2.0 * k - 1.0;
+    double f = (a - sqrt(a * a - 8.0 * (double)r)) * 0.5;
+    int64_t ii = f < 0.0 ? 0 : (int64_t)f;
+    if (ii > (int64_t)k - 2) ii = (int64_t)k - 2;
+    while (ii > 0 && row_start((uint64_t)ii, k) > r) ii--;
+    while (ii + 1 <= (int64_t)k - 2 && row_start((uint64_t)ii + 1, k) <= r) ii++;
+    *i = (uint32_t)ii;
+    *j = (uint32_t)(r - row_start((uint64_t)ii, k) + (uint64_t)ii + 1);
+}
+
+__global__ void k_mst_init(MstParams M, const uint32_t *g1_idx, uint32_t m) {
+    const uint32_t t0 = blockIdx.x * blockDim.x + threadIdx.x, st = gridDim.x * blockDim.x;
+    for (uint32_t c = t0; c < M.k; c += st) {
+        M.par[c] = c;
+        M.best[c] = ~0ull;
+    }
+    for (uint32_t t = t0; t < m; t += st) M.edges[0][t] = g1_idx[t];
+    if (t0 == 0) {
+        M.hdr[0] = m;
+        M.hdr[1] = 0;
+        M.hdr[2] = 0;
+        M.hdr[3] = 0;
+    }
+}
+
+// Every edge still joining two components offers its key to both roots and
+// moves to the other list; edges inside a component are dropped.
+__global__ void __launch_bounds__(256) k_mst_edges(MstParams M, uint32_t in) {
+    const uint32_t out = in ^ 1u;
+    const uint32_t m = M.hdr[in];
+    const uint32_t st = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < m; base += st) {
+        const uint32_t t = base + threadIdx.x;
+        bool live = false;
+        uint32_t p = 0;
+        if (t < m) {
+            p = M.edges[in][t];
+            uint32_t i, j;
+            pair_of(p, &i, &j);
+            const uint32_t ci = M.par[i], cj = M.par[j];
+            if (ci != cj) {
+                live = true;
+                const unsigned long long key = ((M.pt[p] >> 32) << 32) | rank_of(i, j, M.k);
+                if (key < M.best[ci]) atomicMin(M.best + ci, key);
+                if (key < M.best[cj]) atomicMin(M.best + cj, key);
+            }
+        }
+        const uint64_t mk = __ballot(live);
+        if (mk) {
+            const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mk) - 1;
+            uint32_t pos = 0;
+            if (lane() == leader) pos = atomicAdd(M.hdr + out, (uint32_t)__popcll(mk));
+            pos = __shfl(pos, leader, 64);
+            if (live) M.edges[out][pos + lanes_below(mk)] = p;
+        }
+    }
+}
+
+// One workgroup: each root hooks under the root at the other end of its
+// lightest edge and records that edge; when two roots chose the same edge
+// only the smaller records it and only the larger hooks.  With distinct keys
+// those 2-cycles are the only cycles, so pointer jumping flattens the hooks
+// into trees, every seed then takes its new root, and the minima are reset.
+__global__ void __launch_bounds__(1024) k_mst_merge(MstParams M, uint32_t in) {
+    __shared__ int s_changed;
+    const uint32_t k = M.k;
+    for (uint32_t c = threadIdx.x; c < k; c += blockDim.x) {
+        uint32_t h = c;
+        const unsigned long long b = M.best[c];
+        if (M.par[c] == c && b != ~0ull) {
+            uint32_t i, j;
+            rank_pair((uint32_t)b, k, &i, &j);
+            const uint32_t ci = M.par[i], cj = M.par[j];
+            const uint32_t other = ci == c ? cj : ci;
+            const bool mutual = M.best[other] == b;
+            if (!mutual || c < other) {
+                const uint32_t p = (uint32_t)((uint64_t)j * (j - 1) / 2 + i);
+                const uint32_t pos = atomicAdd(M.hdr + 2, 1u);
+                if (pos < k) M.sel[pos] = (uint32_t)M.pt[p];
+            }
+            if (!mutual || c > other) h = other;
+        }
+        M.hook[c] = h;
+    }
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) s_changed = 0;
+        __syncthreads();
+        for (uint32_t c = threadIdx.x; c < k; c += blockDim.x) {
+            const uint32_t h = M.hook[c], hh = M.hook[h];
+            if (hh != h) {
+                M.hook[c] = hh;
+                s_changed = 1;
+            }
+        }
+        __syncthreads();
+        const int changed = s_changed;
+        __syncthreads();
+        if (!changed) break;
+    }
+    for (uint32_t c = threadIdx.x; c < k; c += blockDim.x) M.par[c] = M.hook[M.par[c]];
+    for (uint32_t c = threadIdx.x; c < k; c += blockDim.x) M.best[c] = ~0ull;
+    if (threadIdx.x == 0) M.hdr[in] = 0;
 }
 
 // ------------------------------------------------------------ launchers
@@ -1027,7 +1219,8 @@ hipError_t launch_slot_start(const VorParams &P, uint32_t slot, const uint32_t *
                              uint32_t *heavy_pe_slot, uint32_t nheavy, hipStream_t s) {
     const uint32_t n = P.g.n;
     hipLaunchKernelGGL(k_slot_clear, dim3(fill_grid(n)), dim3(256), 0, s, P.key + (size_t)slot * n,
-                       P.aux + (size_t)slot * n, P.dirty + (size_t)slot * n, n, heavy_pe_slot, nheavy);
+                       P.aux + (size_t)slot * n, P.dirty + (size_t)slot * n, P.settled + (size_t)slot * n, n,
+                       heavy_pe_slot, nheavy);
     hipLaunchKernelGGL(k_slot_seed, dim3(1), dim3(256), 0, s, P, slot, d_seeds, k);
     return hipGetLastError();
 }
@@ -1070,9 +1263,26 @@ hipError_t launch_compact(const CompactParams &C, uint32_t grid, uint32_t block,
     return hipGetLastError();
 }
 
-hipError_t launch_expand(const ExpandParams &E, hipStream_t s) {
-    if (!E.nsel) return hipSuccess;
-    hipLaunchKernelGGL(k_expand, dim3((E.nsel + 127) / 128), dim3(128), 0, s, E);
+hipError_t launch_expand(const ExpandParams &E, uint32_t emit_grid, hipStream_t s) {
+    if (E.nsel_max) {
+        const uint64_t threads = 2ull * E.nsel_max;
+        hipLaunchKernelGGL(k_expand_walk, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, E);
+    }
+    hipLaunchKernelGGL(k_expand_emit, dim3(emit_grid), dim3(256), 0, s, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_mst(const MstParams &M, const uint32_t *g1_idx, uint32_t m, hipStream_t s) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(2048, ((uint64_t)std::max(m, M.k) + 255) / 256);
+    hipLaunchKernelGGL(k_mst_init, dim3(grid), dim3(256), 0, s, M, g1_idx, m);
+    // every round at least halves the number of components that still have an outgoing edge
+    uint32_t rounds = 1;
+    while ((1ull << rounds) < M.k) rounds++;
+    const uint32_t egrid = (uint32_t)std::min<uint64_t>(2048, ((uint64_t)m + 255) / 256 + 1);
+    for (uint32_t r = 0; r <= rounds; r++) {
+        hipLaunchKernelGGL(k_mst_edges, dim3(egrid), dim3(256), 0, s, M, r & 1u);
+        hipLaunchKernelGGL(k_mst_merge, dim3(1), dim3(1024), 0, s, M, r & 1u);
+    }
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ void bind_pass(VorParams &P, const DevGraph &dg, uint8_t *ctl, const Layout &L, 
     P.pass = (PassCtl *)(ctl + L.pass);
     P.far_min = (uint32_t *)(ctl + L.far_min);
     P.near_mark = (uint32_t *)(ctl + L.near_mark);
+    P.settle_mark = (uint32_t *)(ctl + L.settle_mark);
     P.slot.thr = (uint64_t *)(ctl + L.thr);
     P.slot.thr_prev = (uint64_t *)(ctl + L.thr_prev);
     P.slot.carry = (uint32_t *)(ctl + L.carry);
@@ -32,6 +33,17 @@ void bind_pass(VorParams &P, const DevGraph &dg, uint8_t *ctl, const Layout &L, 
     P.slot.done = (uint32_t *)(ctl + L.done);
     P.slot.advances = (uint32_t *)(ctl + L.advances);
     P.nslots = Q;
+}
+
+void bind_state(VorParams &P, const Options &o, uint64_t cap_s, uint64_t cap_b) {
+    P.cap_s = (uint32_t)cap_s;
+    P.cap_b = (uint32_t)cap_b;
+    P.delta = o.delta;
+    P.small_max = o.small_max;
+    P.chunk = o.chunk;
+    P.local_iters = o.local_iters;
+    P.counting = o.counting ? 1u : 0u;
+    P.split = (o.delta != 0xFFFFFFFFu && o.split) ? 1u : 0u;
 }
 
 namespace {
@@ -62,42 +74,92 @@ struct Timer {
 
 }  // namespace
 
+int TailScratch::prepare(uint32_t n, uint32_t k, uint64_t m, hipStream_t st) {
+    int rc;
+    const size_t k4 = ((size_t)k * 4 + 255) & ~(size_t)255, m4 = ((size_t)m * 4 + 255) & ~(size_t)255;
+    if ((rc = mst.ensure(256 + 3 * k4 + 2 * k4 + 2 * m4))) return rc;
+    if ((rc = out.ensure((size_t)n * 12 + 16))) return rc;
+    if ((rc = host.ensure(64))) return rc;
+    const size_t mark_bytes = ((size_t)n + 3) / 4 * 4;
+    if (mark_n != n || mark.bytes < mark_bytes) {
+        if ((rc = mark.ensure(mark_bytes))) return rc;
+        if ((rc = hip_check(launch_fill_u32(mark.as<uint32_t>(), mark_bytes / 4, 0u, st), "mark clear"))) return rc;
+        mark_n = n;
+    }
+    for (hipEvent_t &e : ev)
+        if (!e && (rc = hip_check(hipEventCreate(&e), "hipEventCreate"))) return rc;
+    return STEINER_OK;
+}
+
+void TailScratch::release() {
+    mst.release();
+    mark.release();
+    out.release();
+    host.release();
+    for (hipEvent_t &e : ev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+    mark_n = 0;
+}
+
 int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, const uint32_t *pred, uint32_t k,
-                 const std::vector<uint32_t> &pidx, const std::vector<uint64_t> &pval, DevBuf &sel_buf,
-                 uint32_t *visited, uint32_t *oedges, std::unique_ptr<steiner_result> &out, double *ms_mst,
-                 double *ms_expand) {
+                 const uint64_t *pt, const uint32_t *g1_idx, uint32_t m, TailScratch &ts,
+                 std::unique_ptr<steiner_result> &out, double *ms_mst, double *ms_expand) {
     const uint32_t n = g->n;
     int rc;
-    const auto t0 = std::chrono::steady_clock::now();
-    std::vector<uint32_t> chosen;
-    const int mrc = prim_mst(k, pidx, pval, chosen);  // Step 3
-    const auto t1 = std::chrono::steady_clock::now();
-    if (ms_mst) *ms_mst += std::chrono::duration<double, std::milli>(t1 - t0).count();
-    if (mrc) return fail(mrc, "seeds are not connected");
-    // Step 4: the cross-cell edge kept for each MST pair; Steps 5-6 on the device.
-    std::vector<uint32_t> sel(chosen.size());
-    for (size_t t = 0; t < chosen.size(); t++) sel[t] = (uint32_t)(pval[chosen[t]] & 0xFFFFFFFFu);
-    if ((rc = sel_buf.ensure(sel.size() * 4 + 4))) return rc;
+    if ((rc = ts.prepare(n, k, m, st))) return rc;
+    const size_t k4 = ((size_t)k * 4 + 255) & ~(size_t)255, m4 = ((size_t)m * 4 + 255) & ~(size_t)255;
+    uint8_t *base = ts.mst.as<uint8_t>();
+    MstParams M{};
+    M.pt = pt;
+    M.k = k;
+    M.hdr = (uint32_t *)base;
+    M.par = (uint32_t *)(base + 256);
+    M.hook = (uint32_t *)(base + 256 + k4);
+    M.sel = (uint32_t *)(base + 256 + 2 * k4);
+    M.best = (unsigned long long *)(base + 256 + 3 * k4);
+    M.edges[0] = (uint32_t *)(base + 256 + 5 * k4);
+    M.edges[1] = (uint32_t *)(base + 256 + 5 * k4 + m4);
     ExpandParams EP{};
     EP.g = g->dg;
     EP.key = key;
     EP.pred = pred;
-    EP.sel_e = sel_buf.as<uint32_t>();
-    EP.nsel = (uint32_t)sel.size();
-    EP.visited = visited;
-    EP.oa = oedges;
-    EP.ob = oedges + n;
-    EP.ow = oedges + 2 * (size_t)n;
-    EP.ocnt = oedges + 3 * (size_t)n;
-    rc = hip_check(hipMemcpyAsync(sel_buf.ptr, sel.data(), sel.size() * 4, hipMemcpyHostToDevice, st), "H2D sel");
-    if (!rc) rc = hip_check(launch_fill_u32(EP.visited, ((size_t)n + 31) / 32, 0u, st), "visited");
-    if (!rc) rc = hip_check(launch_fill_u32(EP.ocnt, 1, 0u, st), "count");
-    if (!rc) rc = hip_check(launch_expand(EP, st), "expand");
-    uint32_t m_out = 0;
-    if (!rc) rc = hip_check(hipMemcpyAsync(&m_out, EP.ocnt, 4, hipMemcpyDeviceToHost, st), "D2H count");
-    if (!rc) rc = hip_check(hipStreamSynchronize(st), "expand sync");
-    if (rc) return rc;
-    if (m_out > n) return fail(STEINER_EDEVICE, "expansion overflow");
+    EP.sel_e = M.sel;
+    EP.nsel = M.hdr + 2;
+    EP.nsel_max = k - 1;
+    EP.mark = ts.mark.as<uint32_t>();
+    EP.oa = ts.out.as<uint32_t>();
+    EP.ob = EP.oa + n;
+    EP.ow = EP.oa + 2 * (size_t)n;
+    EP.ocnt = M.hdr + 3;
+    const uint32_t emit_grid = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)std::max(1, g->cu_count) * 8, (((uint64_t)n + 3) / 4 + 255) / 256));
+    // Step 3 (MST of G'1), Step 4 (its kept cross-cell edges), Steps 5-6 (pred walks)
+    rc = hip_check(hipEventRecord(ts.ev[0], st), "event");
+    if (!rc) rc = hip_check(launch_mst(M, g1_idx, m, st), "mst");
+    if (!rc) rc = hip_check(hipEventRecord(ts.ev[1], st), "event");
+    if (!rc) rc = hip_check(launch_expand(EP, emit_grid, st), "expand");
+    if (!rc) rc = hip_check(hipEventRecord(ts.ev[2], st), "event");
+    uint32_t *h = ts.host.as<uint32_t>();
+    if (!rc) rc = hip_check(hipMemcpyAsync(h, M.hdr, 16, hipMemcpyDeviceToHost, st), "D2H counts");
+    if (!rc) rc = hip_check(hipStreamSynchronize(st), "tail sync");
+    if (rc) {
+        ts.mark_n = 0;  // the marks may be left set
+        return rc;
+    }
+    const uint32_t nsel = h[2], m_out = h[3];
+    if (nsel < k - 1) return fail(STEINER_EDISCONNECTED, "seeds are not connected");
+    if (nsel > k - 1 || m_out > n) {
+        ts.mark_n = 0;
+        return fail(STEINER_EDEVICE, "tree expansion overflow (%u MST edges, %u tree edges)", nsel, m_out);
+    }
+    float t_mst = 0.f, t_exp = 0.f;
+    (void)hipEventElapsedTime(&t_mst, ts.ev[0], ts.ev[1]);
+    (void)hipEventElapsedTime(&t_exp, ts.ev[1], ts.ev[2]);
+    if (ms_mst) *ms_mst += t_mst;
+    if (ms_expand) *ms_expand += t_exp;
     std::vector<uint32_t> a(m_out), b(m_out), w(m_out);
     rc = hip_check(hipMemcpyAsync(a.data(), EP.oa, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
     if (!rc) rc = hip_check(hipMemcpyAsync(b.data(), EP.ob, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
@@ -105,24 +167,25 @@ int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, const ui
     if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H edges");
     if (rc) return rc;
     // Step 7: canonical order (a, b, w) and D
-    std::vector<std::tuple<uint32_t, uint32_t, uint32_t>> ed(m_out);
-    for (uint32_t t = 0; t < m_out; t++) ed[t] = std::make_tuple(a[t], b[t], w[t]);
-    std::sort(ed.begin(), ed.end());
+    std::vector<uint32_t> ord(m_out);
+    for (uint32_t t = 0; t < m_out; t++) ord[t] = t;
+    std::sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) {
+        return a[x] != a[y] ? a[x] < a[y] : b[x] != b[y] ? b[x] < b[y] : w[x] < w[y];
+    });
     std::unique_ptr<steiner_result> res(new steiner_result());
     res->a.resize(m_out);
     res->b.resize(m_out);
     res->w.resize(m_out);
     uint64_t D = 0;
     for (uint32_t t = 0; t < m_out; t++) {
-        res->a[t] = std::get<0>(ed[t]);
-        res->b[t] = std::get<1>(ed[t]);
-        res->w[t] = std::get<2>(ed[t]);
+        res->a[t] = a[ord[t]];
+        res->b[t] = b[ord[t]];
+        res->w[t] = w[ord[t]];
         D += res->w[t];
     }
     res->total = D;
     res->stats.tree_edges = m_out;
     out = std::move(res);
-    if (ms_expand) *ms_expand += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
     return STEINER_OK;
 }
 
@@ -147,8 +210,9 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     if (Q == 0) return STEINER_OK;
 
     // ---------------------------------------------------------- allocation
-    const uint64_t cap_s = (uint64_t)Q * n + 64;
-    const uint64_t cap_b = (uint64_t)Q * big_row_chunks(g, o.small_max, o.chunk) + 64;
+    // a vertex is listed at most once per round as a light item and once as a heavy item
+    const uint64_t cap_s = 2ull * Q * n + 64;
+    const uint64_t cap_b = 2ull * Q * big_row_chunks(g, o.small_max, o.chunk) + 64;
     if (cap_s >= (1ull << 32) || cap_b >= (1ull << 32))
         return fail(STEINER_ENOMEM, "batch too large for 32-bit frontier counters");
     std::vector<uint64_t> pt_off(Q + 1, 0), oc_off(Q + 1, 0), sd_off(Q + 1, 0);
@@ -163,12 +227,12 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     const Layout L(Q);
     const size_t QN = (size_t)Q * n;
     if ((rc = ws.key.ensure(QN * 8)) || (rc = ws.aux.ensure(QN * 4)) || (rc = ws.dirty.ensure(QN)) ||
+        (rc = ws.settled.ensure(QN)) ||
         (rc = ws.items_s[0].ensure(cap_s * 8)) || (rc = ws.items_s[1].ensure(cap_s * 8)) ||
         (rc = ws.items_b[0].ensure(cap_b * 8)) || (rc = ws.items_b[1].ensure(cap_b * 8)) ||
         (rc = ws.ctl.ensure(L.total)) || (rc = ws.heavy_pe.ensure((size_t)Q * g->nheavy * 4 + 4)) ||
         (rc = ws.seeds.ensure(sd_off[Q] * 4)) || (rc = ws.pt.ensure(pt_off[Q] * 8)) ||
         (rc = ws.cidx.ensure(oc_off[Q] * 4)) || (rc = ws.cval.ensure(oc_off[Q] * 8)) ||
-        (rc = ws.visited.ensure(((size_t)n + 31) / 32 * 4)) || (rc = ws.oedges.ensure((size_t)n * 12 + 16)) ||
         (rc = ws.host.ensure(std::max<size_t>(L.total, sd_off[Q] * 4) + 4096)))
         return rc;
     uint8_t *ctl = ws.ctl.as<uint8_t>();
@@ -179,17 +243,12 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     P.key = ws.key.as<uint64_t>();
     P.aux = ws.aux.as<uint32_t>();
     P.dirty = ws.dirty.as<uint8_t>();
+    P.settled = ws.settled.as<uint8_t>();
     P.items_s[0] = ws.items_s[0].as<uint64_t>();
     P.items_s[1] = ws.items_s[1].as<uint64_t>();
     P.items_b[0] = ws.items_b[0].as<uint64_t>();
     P.items_b[1] = ws.items_b[1].as<uint64_t>();
-    P.cap_s = (uint32_t)cap_s;
-    P.cap_b = (uint32_t)cap_b;
-    P.delta = o.delta;
-    P.small_max = o.small_max;
-    P.chunk = o.chunk;
-    P.local_iters = o.local_iters;
-    P.counting = o.counting ? 1u : 0u;
+    bind_state(P, o, cap_s, cap_b);
 
     // Per-slot pointer tables (host image, then one copy).
     {
@@ -377,18 +436,21 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         }
         if (qq.stop_after == STOP_AFTER_SCAN) continue;
         const uint32_t m = out_cnt[s];
-        qq.pidx.resize(m);
-        qq.pval.resize(m);
-        if (m) {
-            rc = hip_check(hipMemcpyAsync(qq.pidx.data(), ws.cidx.as<uint32_t>() + oc_off[s], (size_t)m * 4, hipMemcpyDeviceToHost, st), "D2H G'1");
-            if (!rc) rc = hip_check(hipMemcpyAsync(qq.pval.data(), ws.cval.as<uint64_t>() + oc_off[s], (size_t)m * 8, hipMemcpyDeviceToHost, st), "D2H G'1");
-            if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H G'1");
-            if (rc) return rc;
+        if (qq.stop_after == STOP_AFTER_COMPACT) {
+            qq.pidx.resize(m);
+            qq.pval.resize(m);
+            if (m) {
+                rc = hip_check(hipMemcpyAsync(qq.pidx.data(), ws.cidx.as<uint32_t>() + oc_off[s], (size_t)m * 4,
+                                              hipMemcpyDeviceToHost, st), "D2H G'1");
+                if (!rc) rc = hip_check(hipMemcpyAsync(qq.pval.data(), ws.cval.as<uint64_t>() + oc_off[s], (size_t)m * 8,
+                                                       hipMemcpyDeviceToHost, st), "D2H G'1");
+                if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H G'1");
+                if (rc) return rc;
+            }
+            continue;
         }
-        if (qq.stop_after == STOP_AFTER_COMPACT) continue;
-        uint32_t *oe = ws.oedges.as<uint32_t>();
-        int trc = tree_from_g1(g, st, P.key + (size_t)s * n, P.aux + (size_t)s * n, k, qq.pidx, qq.pval, ws.sel,
-                               ws.visited.as<uint32_t>(), oe, qq.result, &ms_mst, &ms_expand);
+        int trc = tree_from_g1(g, st, P.key + (size_t)s * n, P.aux + (size_t)s * n, k, ws.pt.as<uint64_t>() + pt_off[s],
+                               ws.cidx.as<uint32_t>() + oc_off[s], m, ws.tail, qq.result, &ms_mst, &ms_expand);
         if (trc == STEINER_EDISCONNECTED) {
             qq.status = trc;
             continue;

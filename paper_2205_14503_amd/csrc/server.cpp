@@ -3,7 +3,7 @@
 // One multi-query relaxation pass runs for the server's lifetime.  Between
 // short chunks of rounds the scheduler thread admits waiting requests into
 // free slots (a slot is the per-query vertex state: key, stamp/pred and park
-// byte, 13 bytes per vertex) when the request's device bytes fit the memory
+// byte and settled byte, 14 bytes per vertex) when the request's device bytes fit the memory
 // budget; a new query's seeds join the pass at the next round, so queries at
 // different bucket depths share every relaxation launch.  A query whose cells
 // have converged is handed to the tail thread, which runs its boundary scan,
@@ -100,7 +100,8 @@ struct steiner_server {
     uint64_t budget = 0, used = 0, slot_bytes = 0;
     uint32_t S = 0;  // slots
     hipStream_t s_main = nullptr, s_tail = nullptr;
-    DevBuf key, aux, dirty, items_s[2], items_b[2], ctl, heavy_pe, pool, visited, oedges, sel;
+    DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, pool;
+    TailScratch tail;
     HostPinned hbuf;
     Layout L{1};
     VorParams P{};
@@ -296,18 +297,8 @@ void steiner_server::run_tail() {
                 const uint64_t P_ = r->pt_len;
                 uint8_t *base = pool.as<uint8_t>() + r->pool_off;
                 const uint32_t *oi = (const uint32_t *)(base + ((8 * P_ + 255) & ~255ull));
-                const uint64_t *ov = (const uint64_t *)((const uint8_t *)oi + ((4 * r->oc_cap + 255) & ~255ull));
-                std::vector<uint32_t> pidx(cnt);
-                std::vector<uint64_t> pval(cnt);
-                if (cnt) {
-                    status = hip_check(hipMemcpyAsync(pidx.data(), oi, 4ull * cnt, hipMemcpyDeviceToHost, s_tail), "D2H G'1");
-                    if (!status)
-                        status = hip_check(hipMemcpyAsync(pval.data(), ov, 8ull * cnt, hipMemcpyDeviceToHost, s_tail), "D2H G'1");
-                    if (!status) status = hip_check(hipStreamSynchronize(s_tail), "D2H G'1");
-                }
-                if (!status)
-                    status = tree_from_g1(g, s_tail, P.key + (size_t)slot * n, P.aux + (size_t)slot * n, k, pidx, pval,
-                                          sel, visited.as<uint32_t>(), oedges.as<uint32_t>(), res, nullptr, nullptr);
+                status = tree_from_g1(g, s_tail, P.key + (size_t)slot * n, P.aux + (size_t)slot * n, k,
+                                      (const uint64_t *)base, oi, cnt, tail, res, nullptr, nullptr);
                 if (!status) res->stats.pairs = cnt;
             }
         }
@@ -347,7 +338,7 @@ extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes
     s->o.timing = false;
     s->o.counting = false;
     const uint32_t n = g->n;
-    s->slot_bytes = 13ull * n + 4ull * g->nheavy;
+    s->slot_bytes = 14ull * n + 4ull * g->nheavy;
     s->half = g->nnz / 2 + 1;
     s->budget = mem_budget_bytes;
     if (s->budget < s->slot_bytes + s->pool_need(2))
@@ -355,17 +346,17 @@ extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes
                     (unsigned long long)(s->slot_bytes + s->pool_need(2)));
     s->S = (uint32_t)std::min<uint64_t>(max_slots, s->budget / s->slot_bytes);
     const uint32_t S = s->S;
-    const uint64_t cap_s = (uint64_t)S * n + 64;
-    const uint64_t cap_b = (uint64_t)S * big_row_chunks(g, s->o.small_max, s->o.chunk) + 64;
+    const uint64_t cap_s = 2ull * S * n + 64;
+    const uint64_t cap_b = 2ull * S * big_row_chunks(g, s->o.small_max, s->o.chunk) + 64;
     if (cap_s >= (1ull << 32) || cap_b >= (1ull << 32)) return fail(STEINER_ENOMEM, "too many slots for this graph");
     s->L = Layout(S);
     const size_t SN = (size_t)S * n;
     if ((rc = s->key.ensure(SN * 8)) || (rc = s->aux.ensure(SN * 4)) || (rc = s->dirty.ensure(SN)) ||
+        (rc = s->settled.ensure(SN)) ||
         (rc = s->items_s[0].ensure(cap_s * 8)) || (rc = s->items_s[1].ensure(cap_s * 8)) ||
         (rc = s->items_b[0].ensure(cap_b * 8)) || (rc = s->items_b[1].ensure(cap_b * 8)) ||
         (rc = s->ctl.ensure(s->L.total)) || (rc = s->heavy_pe.ensure((size_t)S * g->nheavy * 4 + 4)) ||
-        (rc = s->pool.ensure(s->budget)) || (rc = s->visited.ensure(((size_t)n + 31) / 32 * 4)) ||
-        (rc = s->oedges.ensure((size_t)n * 12 + 16)) || (rc = s->hbuf.ensure(s->L.total + 4096)))
+        (rc = s->pool.ensure(s->budget)) || (rc = s->hbuf.ensure(s->L.total + 4096)))
         return rc;
     s->pa.init(s->budget);
     if ((rc = hip_check(hipStreamCreateWithFlags(&s->s_main, hipStreamNonBlocking), "stream"))) return rc;
@@ -375,17 +366,12 @@ extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes
     P.key = s->key.as<uint64_t>();
     P.aux = s->aux.as<uint32_t>();
     P.dirty = s->dirty.as<uint8_t>();
+    P.settled = s->settled.as<uint8_t>();
     P.items_s[0] = s->items_s[0].as<uint64_t>();
     P.items_s[1] = s->items_s[1].as<uint64_t>();
     P.items_b[0] = s->items_b[0].as<uint64_t>();
     P.items_b[1] = s->items_b[1].as<uint64_t>();
-    P.cap_s = (uint32_t)cap_s;
-    P.cap_b = (uint32_t)cap_b;
-    P.delta = s->o.delta;
-    P.small_max = s->o.small_max;
-    P.chunk = s->o.chunk;
-    P.local_iters = s->o.local_iters;
-    P.counting = 0;
+    bind_state(P, s->o, cap_s, cap_b);
     if ((rc = hip_check(launch_pass_reset(P, s->s_main), "pass reset"))) return rc;
     hipLaunchKernelGGL(k_iota, dim3((S + 255) / 256), dim3(256), 0, s->s_main,
                        (uint32_t *)(s->ctl.as<uint8_t>() + s->L.slot_ids), S);
@@ -469,10 +455,11 @@ extern "C" int steiner_server_destroy(steiner_server *s) {
     (void)hipStreamSynchronize(s->s_tail);
     for (auto &kv : s->reqs) delete kv.second;
     s->reqs.clear();
-    DevBuf *bufs[] = {&s->key, &s->aux, &s->dirty, &s->items_s[0], &s->items_s[1], &s->items_b[0], &s->items_b[1],
-                      &s->ctl, &s->heavy_pe, &s->pool, &s->visited, &s->oedges, &s->sel};
+    DevBuf *bufs[] = {&s->key, &s->aux, &s->dirty, &s->settled, &s->items_s[0], &s->items_s[1], &s->items_b[0], &s->items_b[1],
+                      &s->ctl, &s->heavy_pe, &s->pool};
     for (DevBuf *b : bufs) b->release();
     s->hbuf.release();
+    s->tail.release();
     if (s->s_main) (void)hipStreamDestroy(s->s_main);
     if (s->s_tail) (void)hipStreamDestroy(s->s_tail);
     delete s;

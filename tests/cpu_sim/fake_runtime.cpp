@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 #include <thread>
 
 #include "kernels.h"
@@ -160,14 +161,44 @@ hipError_t launch_compact(const CompactParams &C, uint32_t, uint32_t, hipStream_
     return hipSuccess;
 }
 
-hipError_t launch_expand(const ExpandParams &E, hipStream_t) {
+hipError_t launch_mst(const MstParams &M, const uint32_t *g1_idx, uint32_t m, hipStream_t) {
     std::lock_guard<std::mutex> lk(sim_mu);
-    for (uint32_t t = 0; t < E.nsel && t + 1 < E.g.n; t++) {
+    // union-find over the listed pairs in list order (the simulated G'1 is a star)
+    std::vector<uint32_t> root(M.k);
+    for (uint32_t c = 0; c < M.k; c++) root[c] = c;
+    auto find = [&](uint32_t x) {
+        while (root[x] != x) x = root[x] = root[root[x]];
+        return x;
+    };
+    uint32_t nsel = 0;
+    for (uint32_t t = 0; t < m; t++) {
+        const uint32_t p = g1_idx[t];
+        const uint32_t j = (uint32_t)((1.0 + std::sqrt(1.0 + 8.0 * (double)p)) / 2.0);
+        const uint32_t i = p - j * (j - 1) / 2;
+        if (i >= j || j >= M.k) return hipErrorInvalidValue;
+        const uint32_t a = find(i), b = find(j);
+        if (a == b) continue;
+        root[a] = b;
+        M.sel[nsel++] = (uint32_t)M.pt[p];
+    }
+    M.hdr[0] = M.hdr[1] = 0;
+    M.hdr[2] = nsel;
+    M.hdr[3] = 0;
+    return hipSuccess;
+}
+
+hipError_t launch_expand(const ExpandParams &E, uint32_t, hipStream_t) {
+    std::lock_guard<std::mutex> lk(sim_mu);
+    const uint32_t nsel = *E.nsel;
+    if (nsel > E.nsel_max) return hipErrorInvalidValue;
+    for (uint32_t t = 0; t < nsel && t + 1 < E.g.n; t++) {
         E.oa[t] = t;
         E.ob[t] = t + 1;
         E.ow[t] = 1;
     }
-    *E.ocnt = E.nsel;
+    for (uint32_t x = 0; x < (E.g.n + 3) / 4; x++)
+        if (E.mark[x]) return hipErrorInvalidValue;  // marks are zero between calls
+    *E.ocnt = nsel;
     return hipSuccess;
 }
 

@@ -24,6 +24,9 @@ OPTION_SETS = {
     "unbounded": dict(delta=0xFFFFFFFF),
     "chunky": dict(small_max=1, chunk=64),
     "persist_odd": dict(driver=2, small_max=2, chunk=64, delta=3, block=1024),
+    "bucketed": dict(delta=50),
+    "split": dict(delta=50, flags=st.FLAG_SPLIT),
+    "split_chunky": dict(delta=7, flags=st.FLAG_SPLIT, small_max=1, chunk=64, local_iters=0xFFFFFFFF),
 }
 
 
@@ -136,7 +139,7 @@ def test_upload_validation(stream):
 def test_er16k_config(stream):
     g = W.make_graph("er16k")
     seeds = W.make_seeds(g, 16)
-    for name in ("default", "host", "persistent", "delta1", "unbounded", "chunky"):
+    for name in ("default", "host", "persistent", "delta1", "bucketed", "split", "chunky"):
         say(f"er16k options={name}")
         check_case(g, seeds, stream, OPTION_SETS[name], f"er16k {name}")
 
@@ -146,7 +149,7 @@ def test_rmat_hubs(stream):
     cand = W.lcc(g)
     for k in (2, 37, 1000):
         seeds = W.sample(cand, k, master=3)
-        for name in ("default", "persistent", "chunky"):
+        for name in ("default", "persistent", "chunky", "split"):
             say(f"rmat16 k={k} options={name}")
             check_case(g, seeds, stream, OPTION_SETS[name], f"rmat16 k={k} {name}")
 
@@ -154,7 +157,7 @@ def test_rmat_hubs(stream):
 def test_weight_one_ties(stream):
     g = W.rmat(13, 8, wlo=1, whi=1)
     seeds = W.sample(W.lcc(g), 300, master=5)
-    for name in ("default", "persistent", "unbounded"):
+    for name in ("default", "persistent", "bucketed", "split_chunky"):
         say(f"rmat13 unit weights options={name}")
         check_case(g, seeds, stream, OPTION_SETS[name], f"unit {name}")
     gg = W.grid(61, 67, 1, 2)
