@@ -25,19 +25,82 @@ sys.path.insert(0, ROOT)
 METRIC = "GTEPS + Steiner queries/s at 1 GPU (bit-exact vs oracle); p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2205_14503_amd", "csrc", "kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2205_14503_amd", "csrc", f)
+              for f in ("kernels.hip", "kernels.h", "common.h", "engine.cpp", "pass.cpp")]
 
 
 def algorithmic_bytes(n: int, nnz_reached: int, nnz: int):
-    """Bytes a work-efficient pass must move (layout: u32 row offsets, 8-byte
-    (col, w) entries, 8-byte keys, 4-byte pred)."""
-    b_vor = 8 * nnz_reached + 4 * (n + 1) + 16 * n
-    b_scan = 8 * nnz + 4 * (n + 1) + 20 * n
+    """Bytes a work-efficient pass must move: every (col, w) entry once (8 B),
+    the row offsets once (8 B each, counted as 64-bit whatever the device
+    layout), the key written at set-up and read at the end (16 B per vertex),
+    and for the scan the key streamed and gathered once plus pred written
+    (20 B per vertex)."""
+    b_vor = 8 * nnz_reached + 8 * (n + 1) + 16 * n
+    b_scan = 8 * nnz + 8 * (n + 1) + 20 * n
     return b_vor, b_scan
 
 
+def copy_calibration(torch, mib: int = 1024, reps: int = 3):
+    """A plain device copy of known size, for scaling the FETCH_SIZE /
+    WRITE_SIZE counters to bytes."""
+    x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": mib << 20, "bytes_written": mib << 20, "reps": reps}}),
+          flush=True)
+
+
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources that decide what the relaxation kernel does."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _pmc_per_kernel(path: str):
+    """Mean counter value (KiB) per dispatch, by kernel, from a rocprofv3
+    counter_collection.csv."""
+    import csv
+    acc = {}
+    for row in csv.DictReader(open(path)):
+        name = row["Kernel_Name"].split("(")[0]
+        name = name.split("::")[-1].split("<")[0] if "stn::" in name else name
+        acc.setdefault(name, []).append(float(row["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def pmc_summary(args):
+    """profiles/traffic.json entry + a text summary from two counter runs of
+    bench.py (FETCH_SIZE, WRITE_SIZE) and two of the copy calibration."""
+    fetch, write, cfetch, cwrite = args.pmc_summary
+    copy_kib = 1 << 20  # the calibration copies 1 GiB
+    f_scale = copy_kib / _pmc_per_kernel(cfetch)["__amd_rocclr_copyBuffer"][0]
+    w_scale = copy_kib / _pmc_per_kernel(cwrite)["__amd_rocclr_copyBuffer"][0]
+    fk, wk = _pmc_per_kernel(fetch), _pmc_per_kernel(write)
+    entry = {"kernel_sha": kernel_sha(), "kernel": "k_round",
+             "config": {"delta": args.delta or None, "local_iters": args.local or None},
+             "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4), "per_kernel": {}}
+    lines = ["| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | scaled MB/dispatch |",
+             "|---|---|---|---|---|"]
+    for name in sorted(fk, key=lambda x: -fk[x][0] * fk[x][1]):
+        fv, cnt = fk[name]
+        wv = wk.get(name, (0.0, 0))[0]
+        mb = (fv * f_scale + wv * w_scale) * 1024 / 1e6
+        entry["per_kernel"][name] = {"dispatches": cnt, "fetch_kib": round(fv, 3), "write_kib": round(wv, 3),
+                                     "bytes": round(mb * 1e6)}
+        lines.append(f"| {name} | {cnt} | {fv:.1f} | {wv:.1f} | {mb:.3f} |")
+    entry["bytes_per_launch"] = entry["per_kernel"]["k_round"]["bytes"]
+    data = json.load(open(TRAFFIC_FILE)) if os.path.exists(TRAFFIC_FILE) else {}
+    data[args.workload] = entry
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    print(f"calibration: copy of 1 GiB reads {copy_kib / f_scale:.1f} KiB FETCH_SIZE (x{f_scale:.4f}), "
+          f"writes {copy_kib / w_scale:.1f} KiB WRITE_SIZE (x{w_scale:.4f})")
+    print("\n".join(lines))
 
 
 def bench_batch(args, st, W, np, torch, stream):
@@ -153,7 +216,14 @@ def main():
     ap.add_argument("--seq-sample", type=int, default=30, help="serving: queries solved alone to set the rate")
     ap.add_argument("--slots", type=int, default=32, help="serving: resident query slots")
     ap.add_argument("--budget-gb", type=int, default=96, help="serving: device memory budget")
+    ap.add_argument("--local", type=int, default=0, help="local-queue depth (with --delta: skips the tuner)")
+    ap.add_argument("--copy-calib", action="store_true", help="run only the copy kernel used to scale HBM counters")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the workload's entry of profiles/traffic.json from rocprofv3 counter runs")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)
@@ -166,6 +236,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        copy_calibration(torch)
+        return
     stream = torch.cuda.current_stream()
     spec = W.WORKLOADS[args.workload]
     if "queries" in spec:
@@ -189,17 +262,22 @@ def main():
         opts["driver"] = args.driver
     if args.delta:
         opts["delta"] = args.delta
+    if args.local:
+        opts["local_iters"] = args.local
     dg = st.Graph(g, 0, stream)
     tuned = None
     if not args.no_tune and not args.delta:
         t0 = time.time()
         tuned = dg.tune(seeds)  # set-up, like the upload: picks delta and the local-queue depth
-        tuned = {"delta": tuned["delta"], "local_iters": tuned["local_iters"], "seconds": round(time.time() - t0, 2)}
+        tuned = {"delta": tuned["delta"], "local_iters": tuned["local_iters"],
+                 "split": bool(tuned["flags"] & st.FLAG_SPLIT), "lazy_pred": bool(tuned["flags"] & st.FLAG_LAZY_PRED),
+                 "seconds": round(time.time() - t0, 2)}
         print(f"[bench] tuned {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         tree = dg.solve(seeds, opts)
     torch.cuda.synchronize()
     lat, relax_ms, relax_launches, scan_ms, voronoi_ms, rounds = [], [], [], [], [], []
+    phase_ms = {p: [] for p in ("init", "voronoi", "scan", "compact", "mst", "expand", "total")}
     t_start = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
@@ -210,6 +288,8 @@ def main():
         scan_ms.append(tree.stats["ms_scan"])
         voronoi_ms.append(tree.stats["ms_voronoi"])
         rounds.append(tree.stats["rounds"])
+        for p in phase_ms:
+            phase_ms[p].append(tree.stats["ms_" + p])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed * 1e3 / args.steps
@@ -229,7 +309,10 @@ def main():
         try:
             tf = json.load(open(TRAFFIC_FILE))
             ent = tf.get(args.workload)
-            if ent and ent.get("kernel_sha") == kernel_sha():
+            used = {"delta": opts.get("delta", tuned and tuned["delta"]),
+                    "local_iters": opts.get("local_iters", tuned and tuned["local_iters"])}
+            used = {key: (int(val) if val else None) for key, val in used.items()}
+            if ent and ent.get("kernel_sha") == kernel_sha() and ent.get("config") == used:
                 traffic = ent["bytes_per_launch"]
         except Exception:
             traffic = None
@@ -273,8 +356,11 @@ def main():
         "queries_per_s": round(1e3 / ms_per_step, 3),
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
-        "phases_ms": {"voronoi": round(float(np.mean(voronoi_ms)), 4), "relax_kernels": round(mean_relax, 4),
-                      "scan": round(mean_scan, 4), "rounds": float(np.mean(rounds))},
+        "gteps_voronoi": round((nnz_reached / 2) / (float(np.mean(voronoi_ms)) * 1e-3) / 1e9, 4),
+        "gteps_voronoi_scan": round((nnz_reached / 2) / ((float(np.mean(voronoi_ms)) + mean_scan) * 1e-3) / 1e9, 4),
+        "phases_ms": dict({p: round(float(np.mean(v)), 4) for p, v in phase_ms.items()},
+                          relax_kernels=round(mean_relax, 4), rounds=float(np.mean(rounds)),
+                          relax_launches=float(np.mean(relax_launches))),
         "tree": {"edges": len(tree.a), "D": tree.total},
         "tuned": tuned,
         "roofline": roofline,

@@ -84,6 +84,10 @@ typedef struct steiner_options {
 #define STEINER_FLAG_SPLIT 4u    /* within a bucket relax edges of weight <= delta first and the
                                     heavier ones once per settled vertex (Delta-stepping's
                                     light/heavy split); no effect with an unbounded bucket */
+#define STEINER_FLAG_LAZY_PRED 8u  /* the boundary scan gathers each edge's far key once and the tree
+                                      walks find the preds of ordinary rows (dense graphs) */
+#define STEINER_FLAG_EAGER_PRED 16u /* the boundary scan also finds every pred (sparse, high-diameter
+                                       graphs); without either flag the graph's default applies */
 
 /* Per-solve statistics (filled for steiner_solve / steiner_solve_batch results). */
 typedef struct steiner_stats {

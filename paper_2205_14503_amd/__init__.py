@@ -30,6 +30,8 @@ CODE_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDISCONNECTED: "EDIS
 FLAG_TIMING = 1
 FLAG_COUNTERS = 2
 FLAG_SPLIT = 4
+FLAG_LAZY_PRED = 8
+FLAG_EAGER_PRED = 16
 MAX_SEEDS = 92682
 DRIVER_DEFAULT, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
 

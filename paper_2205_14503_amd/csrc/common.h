@@ -107,6 +107,7 @@ struct VorParams {
     uint32_t local_iters; // batches of the wave-local queue expanded per unit (0 = no local queue)
     uint32_t counting;    // 1: accumulate Counters::ev
     uint32_t split;       // 1: light/heavy edge split (finite delta)
+    uint32_t lq_mode;     // bit 0: drain the local queue smallest distance first; bit 1: skip superseded entries
 };
 
 enum : uint32_t {

@@ -122,6 +122,12 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
     r.timing = false;
     r.counting = false;
     r.split = g->tuned_split != 0;
+    r.lq_mode = 3;  // local queue drained smallest distance first, superseded entries skipped
+    // lazy preds pay one row scan per tree vertex to save half the scan's gathers: a win on
+    // dense graphs, a loss on sparse high-diameter ones (long walks, cheap scan)
+    r.lazy_pred = g->tuned_pred ? g->tuned_pred == 2 : (g->n && (double)g->nnz / g->n >= 8.0);
+    if (const char *s = getenv("STEINER_LAZY_PRED")) r.lazy_pred = atoi(s) != 0;
+    if (const char *s = getenv("STEINER_LQ_MODE")) r.lq_mode = (uint32_t)atoi(s);
     if (const char *s = getenv("STEINER_DRIVER")) r.driver = (uint32_t)atoi(s);
     if (const char *s = getenv("STEINER_LOCAL")) r.local_iters = (uint32_t)strtoul(s, nullptr, 10);
     if (const char *s = getenv("STEINER_DELTA")) r.delta = (uint32_t)strtoul(s, nullptr, 10);
@@ -136,6 +142,8 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
         r.timing = (o->flags & STEINER_FLAG_TIMING) != 0;
         r.counting = (o->flags & STEINER_FLAG_COUNTERS) != 0;
         if (o->flags & STEINER_FLAG_SPLIT) r.split = true;
+        if (o->flags & STEINER_FLAG_LAZY_PRED) r.lazy_pred = true;
+        if (o->flags & STEINER_FLAG_EAGER_PRED) r.lazy_pred = false;
     }
     if (r.delta == 0) r.delta = 1;
     if (r.block < 64 || r.block > 1024 || r.block % 64) r.block = 256;
@@ -488,42 +496,55 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
                                     (uint32_t)std::max(1.0, 4 * w), (uint32_t)std::max(1.0, 16 * w), 0xFFFFFFFFu};
     std::sort(deltas.begin(), deltas.end());
     deltas.erase(std::unique(deltas.begin(), deltas.end()), deltas.end());
-    const uint32_t locals[] = {2, 8, 32};
-    double best = 1e300;
+    // coarse to fine: the bucket width at the default queue depth, then the depth, then the split
+    const bool lazy_default = resolve_options(g, nullptr).lazy_pred;
+    auto measure = [&](uint32_t d, uint32_t l, uint32_t split, double *t_out, bool lazy) -> int {
+        Options o = resolve_options(g, nullptr);
+        o.delta = d;
+        o.local_iters = l;
+        o.split = split != 0 && d != 0xFFFFFFFFu;
+        o.lazy_pred = lazy;
+        double t_min = 1e300;
+        for (int rep = 0; rep < 2; rep++) {
+            std::vector<Query> qs(1);
+            qs[0].S = S;
+            const auto t0 = std::chrono::steady_clock::now();
+            int e = run_pass(g, o, qs);
+            if (e) return e;
+            const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (qs[0].status && qs[0].status != STEINER_EDISCONNECTED && qs[0].status != STEINER_EOVERFLOW)
+                return qs[0].status;
+            t_min = std::min(t_min, t);
+        }
+        *t_out = t_min;
+        return STEINER_OK;
+    };
+    double best = 1e300, t;
     uint32_t best_d = g->default_delta, best_l = 8, best_split = 0;
-    for (uint32_t d : deltas)
-        for (uint32_t l : locals)
-            for (uint32_t split = 0; split < (d == 0xFFFFFFFFu ? 1u : 2u); split++) {
-                Options o = resolve_options(g, nullptr);
-                o.delta = d;
-                o.local_iters = l;
-                o.split = split != 0;
-                double t_min = 1e300;
-                for (int rep = 0; rep < 2; rep++) {
-                    std::vector<Query> qs(1);
-                    qs[0].S = S;
-                    const auto t0 = std::chrono::steady_clock::now();
-                    if ((rc = run_pass(g, o, qs))) return rc;
-                    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-                    if (qs[0].status && qs[0].status != STEINER_EDISCONNECTED && qs[0].status != STEINER_EOVERFLOW)
-                        return qs[0].status;
-                    t_min = std::min(t_min, t);
-                }
-                if (t_min < best) {
-                    best = t_min;
-                    best_d = d;
-                    best_l = l;
-                    best_split = split;
-                }
-            }
+    for (uint32_t d : deltas) {
+        if ((rc = measure(d, 8, 0, &t, lazy_default))) return rc;
+        if (t < best) { best = t; best_d = d; }
+    }
+    for (uint32_t l : {2u, 4u, 16u, 32u}) {
+        if ((rc = measure(best_d, l, 0, &t, lazy_default))) return rc;
+        if (t < best) { best = t; best_l = l; }
+    }
+    if (best_d != 0xFFFFFFFFu) {
+        if ((rc = measure(best_d, best_l, 1, &t, lazy_default))) return rc;
+        if (t < best) { best = t; best_split = 1; }
+    }
+    bool best_lazy = lazy_default;
+    if ((rc = measure(best_d, best_l, best_split, &t, !lazy_default))) return rc;
+    if (t < best) { best = t; best_lazy = !lazy_default; }
     g->tuned_delta = best_d;
     g->tuned_local = best_l;
     g->tuned_split = best_split;
+    g->tuned_pred = best_lazy ? 2 : 1;
     if (out) {
         memset(out, 0, sizeof(*out));
         out->delta = best_d;
         out->local_iters = best_l;
-        out->flags = best_split ? STEINER_FLAG_SPLIT : 0u;
+        out->flags = (best_split ? STEINER_FLAG_SPLIT : 0u) | (best_lazy ? STEINER_FLAG_LAZY_PRED : STEINER_FLAG_EAGER_PRED);
     }
     return STEINER_OK;
 }

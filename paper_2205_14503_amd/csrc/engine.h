@@ -36,8 +36,9 @@ struct HostPinned {
 };
 
 struct Options {
-    uint32_t delta, driver, block, grid, small_max, chunk, local_iters;
+    uint32_t delta, driver, block, grid, small_max, chunk, local_iters, lq_mode;
     bool timing, counting, split;
+    bool lazy_pred;  // pred of ordinary rows found by the tree walks instead of the scan
 };
 
 // Device buffers of Alg. 2 Steps 3-7 for one query at a time: the MST's
@@ -57,12 +58,15 @@ struct Workspace {
     DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, seeds, pt, cidx, cval, ptrs;
     HostPinned host;
     TailScratch tail;
+    std::vector<hipEvent_t> events;  // timing mode: reused event pool
     void release() {
         DevBuf *all[] = {&key, &aux, &dirty, &settled, &items_s[0], &items_s[1], &items_b[0], &items_b[1], &ctl, &heavy_pe,
                          &seeds, &pt, &cidx, &cval, &ptrs};
         for (DevBuf *b : all) b->release();
         host.release();
         tail.release();
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        events.clear();
     }
 };
 
@@ -135,6 +139,7 @@ struct steiner_graph {
     uint32_t tuned_delta = 0;    // set by steiner_graph_tune
     uint32_t tuned_local = 0;
     uint32_t tuned_split = 0;
+    uint32_t tuned_pred = 0;     // 0: untuned, 1: eager, 2: lazy
     double avg_w = 1.0;
     int cu_count = 256;
     std::mutex mu;               // serialises solves on this graph
@@ -162,8 +167,8 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs);
 // indices g1_idx into its pair table pt), the kept cross-cell edges, the pred
 // walks and D.  key / pred are the query's slot arrays.  The tree's edges come
 // back sorted by (a, b, w); EDISCONNECTED if the MST has fewer than k-1 edges.
-int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, const uint32_t *pred, uint32_t k,
-                 const uint64_t *pt, const uint32_t *g1_idx, uint32_t m, TailScratch &ts,
+int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
+                 const uint64_t *pt, const uint32_t *g1_idx, uint32_t m, bool pred_ready, TailScratch &ts,
                  std::unique_ptr<steiner_result> &out, double *ms_mst, double *ms_expand);
 void pair_from_index(uint64_t p, uint32_t *i, uint32_t *j);
 int canon_seeds(const steiner_graph *g, const uint32_t *seeds, uint32_t k, std::vector<uint32_t> &S);

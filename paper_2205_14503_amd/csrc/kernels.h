@@ -13,6 +13,8 @@ struct ScanParams {
     const uint32_t *slot_ids; // slots to scan
     uint32_t nscan;        // number of slots in slot_ids
     uint32_t *slot_err;    // [slots] ERR_DIST_OVERFLOW / ERR_SUM_OVERFLOW per query
+    uint32_t with_pred;    // 1: pred of every vertex; 0: pred of rows above scan_heavy only (the tree
+                           // expansion finds the others), and each edge's key gathered from one side only
 };
 
 struct CompactParams {
@@ -30,13 +32,14 @@ struct CompactParams {
 struct ExpandParams {
     DevGraph g;
     const uint64_t *key;     // slot base
-    const uint32_t *pred;    // slot base
+    uint32_t *pred;          // slot base: pred of rows above scan_heavy on entry; the walks add the others
     const uint32_t *sel_e;   // chosen cross-cell edge ids (CSR offsets)
     const uint32_t *nsel;    // their number (device)
     uint32_t nsel_max;       // upper bound of *nsel, sizes the launch
     uint32_t *mark;          // n bytes (rounded up to 4), all zero on entry and again on exit
     uint32_t *oa, *ob, *ow;  // output edges, capacity n
     uint32_t *ocnt;          // output count, zero on entry
+    uint32_t pred_ready;     // 1: pred holds every vertex's pred (the scan ran with pred)
 };
 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t count, uint64_t value, hipStream_t s);

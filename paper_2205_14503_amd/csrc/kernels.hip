@@ -16,8 +16,10 @@
 // range 64 edges per step (coalesced 8-byte (col, w) loads).  Larger rows are
 // pushed as fixed chunks that any wave can take, so hubs spread over the GPU.
 //
-// Step 2 (Alg. 5) and the canonical predecessor share one streaming pass over
-// the CSR: every entry gathers its neighbour's key once.
+// Step 2 (Alg. 5) is one streaming pass over the CSR that gathers each edge's
+// far key from its smaller endpoint only.  The canonical predecessor is found
+// where it is needed: by the tree walks for ordinary rows, by the scan for
+// rows above scan_heavy (and for every row when the caller asks for pred).
 #include <algorithm>
 
 #include "kernels.h"
@@ -118,6 +120,7 @@ DEVI void append_b(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, 
 // hop).  Anything the queue cannot hold goes to the next round's list.
 constexpr uint32_t LQ_CAP = 128;
 constexpr uint32_t OUT_CAP = 128;
+static_assert(LQ_CAP == 128, "lq_select packs a 7-bit ring position");
 
 struct WaveScratch {
     uint32_t incl[64];
@@ -362,6 +365,67 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
     }
 }
 
+// The 64 smallest-distance entries of the local queue's cnt > 64 entries at
+// ring positions [h, h + cnt) are returned in the lanes' registers; the others
+// move to [h + 64, h + cnt).  Bitonic: each half is sorted across the wave
+// (the second half in reverse), then one min/max step splits them.  The sort
+// key is the distance, clamped, with the ring position as payload; order only
+// steers the work, never the result.
+DEVI void lq_select(WaveScratch *L, uint32_t h, uint32_t cnt, uint64_t &item, uint64_t &kv, uint32_t &beg,
+                    uint32_t &deg) {
+    const uint32_t ln = lane();
+    uint32_t a[2];
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        const uint32_t i = ln + 64 * j;
+        a[j] = 0xFFFFFFFFu;
+        if (i < cnt) {
+            const uint32_t pos = (h + i) % LQ_CAP;
+            const uint32_t d = (uint32_t)(L->lq_key[pos] >> 32);
+            a[j] = (min(d, (1u << 25) - 2) << 7) | pos;
+        }
+    }
+#pragma unroll
+    for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (uint32_t d = k >> 1; d > 0; d >>= 1) {
+            const bool lower = (ln & d) == 0;
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                const uint32_t p = (uint32_t)__shfl_xor((int)a[j], (int)d, 64);
+                const bool asc = ((ln & k) == 0) != (j == 1);
+                a[j] = (lower == asc) ? min(a[j], p) : max(a[j], p);
+            }
+        }
+    }
+    const uint32_t lo = min(a[0], a[1]), hi = max(a[0], a[1]);
+    const uint32_t pb = lo & (LQ_CAP - 1);
+    item = L->lq_item[pb];
+    kv = L->lq_key[pb];
+    beg = L->lq_beg[pb];
+    deg = L->lq_deg[pb];
+    const bool rest = hi != 0xFFFFFFFFu;
+    const uint32_t pr = hi & (LQ_CAP - 1);
+    uint64_t r_item = 0, r_key = 0;
+    uint32_t r_beg = 0, r_deg = 0;
+    if (rest) {
+        r_item = L->lq_item[pr];
+        r_key = L->lq_key[pr];
+        r_beg = L->lq_beg[pr];
+        r_deg = L->lq_deg[pr];
+    }
+    const uint64_t m = __ballot(rest);
+    wave_sync();
+    if (rest) {
+        const uint32_t at = (h + 64 + lanes_below(m)) % LQ_CAP;
+        L->lq_item[at] = r_item;
+        L->lq_key[at] = r_key;
+        L->lq_beg[at] = r_beg;
+        L->lq_deg[at] = r_deg;
+    }
+    wave_sync();
+}
+
 // Expand the wave's local queue for at most `budget` batches of 64 (each
 // entry carries the key it was improved to: a later improvement of the same
 // vertex queues or lists it again), then move what is left to the next
@@ -369,15 +433,27 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
 DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr, WaveScratch *L, uint32_t budget,
                       uint32_t &h, uint32_t &t) {
     for (uint32_t it = 0; it < budget && h != t; it++) {
-        const uint32_t take = min(t - h, 64u);
+        const uint32_t cnt = t - h;
+        const uint32_t take = min(cnt, 64u);
         wave_sync();
-        const bool has = lane() < take;
-        const uint32_t at = (h + lane()) % LQ_CAP;
-        const uint64_t item = has ? L->lq_item[at] : 0;
-        const uint64_t kv = has ? L->lq_key[at] : KEY_INF;
-        const uint32_t beg = has ? L->lq_beg[at] : 0;
-        const uint32_t deg = has ? L->lq_deg[at] : 0;
+        uint64_t item = 0, kv = KEY_INF;
+        uint32_t beg = 0, deg = 0;
+        if ((P.lq_mode & 1u) && cnt > 64) {
+            lq_select(L, h, cnt, item, kv, beg, deg);
+        } else if (lane() < take) {
+            const uint32_t at = (h + lane()) % LQ_CAP;
+            item = L->lq_item[at];
+            kv = L->lq_key[at];
+            beg = L->lq_beg[at];
+            deg = L->lq_deg[at];
+        }
         h += take;
+        if ((P.lq_mode & 2u) && kv != KEY_INF) {  // superseded: a smaller key of this vertex is queued elsewhere
+            if (ld_agent(P.key + (size_t)s_slot(item) * P.g.n + (uint32_t)item) < kv) {
+                deg = 0;
+                kv = KEY_INF;
+            }
+        }
         expand_items(P, R, thr, s_slot(item), (uint32_t)item, kv, beg, deg, false, L, true, h, t);
     }
     while (h != t) {
@@ -531,7 +607,9 @@ DEVI void advance_body(const VorParams &P, const uint64_t *thr, const uint64_t *
 // One round per launch: the advance scan decided at the end of the previous
 // round (its pushes are processed one round later), the relaxation of this
 // round's list, and, in the last workgroup to finish, the bucket decision.
-__global__ void __launch_bounds__(1024) k_round(VorParams P) {
+// 256-thread workgroups (the host clamps the block size); at most 96 VGPRs,
+// so that five waves per SIMD fit (the default grid assumes five workgroups per CU).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_round(VorParams P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     WaveScratch *s_wave = (WaveScratch *)dyn_smem;
     __shared__ int s_last, s_adv, s_act;
@@ -614,7 +692,7 @@ DEVI bool grid_barrier(Counters *cn, uint32_t nblocks, PassCtl *pass, int *s_abo
     return *s_abort == 0;
 }
 
-__global__ void __launch_bounds__(1024) k_persistent(VorParams P, uint32_t max_rounds) {
+__global__ void __launch_bounds__(256) k_persistent(VorParams P, uint32_t max_rounds) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     WaveScratch *s_wave = (WaveScratch *)dyn_smem;
     __shared__ uint64_t s_thr[PERSIST_SLOTS], s_thr_prev[PERSIST_SLOTS];
@@ -817,9 +895,16 @@ DEVI void boundary_candidate(uint64_t *pt, uint32_t *err, uint64_t krow, uint64_
     if (val < *p) atomicMin((unsigned long long *)p, (unsigned long long)val);
 }
 
+// One wave scans the rows of group grp (64 consecutive vertices of at most
+// scan_heavy entries each), 64 entries per step.  Every edge {a, b}, a < b,
+// is a boundary candidate from row a.  With pred, every entry of a reached
+// row gathers its neighbour's key (the first qualifying entry of the row is
+// pred); without, only entries a -> b with a < b do, unreached rows included,
+// which still sees every edge once for the overflow test.
 DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *pred, uint64_t *pt, uint32_t *err,
                            uint32_t grp, ScanWave *L) {
     const uint32_t n = S.g.n, ln = lane();
+    const bool wp = S.with_pred != 0;
     const uint32_t row = grp * 64 + ln;
     uint64_t kv = KEY_INF;
     uint32_t beg = 0, deg = 0, found = 1;
@@ -828,12 +913,19 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
         const uint32_t b0 = S.g.rp[row], d0 = S.g.rp[row + 1] - b0;
         if (d0 <= S.g.scan_heavy) {
             if (kv == KEY_INF) {
-                pred[row] = NONE;
+                if (wp) {
+                    pred[row] = NONE;
+                } else {
+                    beg = b0;
+                    deg = d0;
+                }
             } else {
                 beg = b0;
                 deg = d0;
-                if ((kv >> 32) == 0) pred[row] = row;  // a seed is its own predecessor
-                else found = 0;
+                if (wp) {
+                    if ((kv >> 32) == 0) pred[row] = row;  // a seed is its own predecessor
+                    else found = 0;
+                }
             }
         }
     }
@@ -863,28 +955,38 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
         const uint32_t rj = L->row[j];
         uint32_t u = 0, w = 0;
         uint64_t ku = KEY_INF;
+        bool need = false;
         if (valid) {
             const uint2 a = S.g.adj[e];
             u = a.x;
             w = a.y;
-            ku = key[u];
-            if (ku == KEY_INF) set_err(err, ERR_DIST_OVERFLOW);
+            need = wp || rj < u;
+            if (need) {
+                ku = key[u];
+                if ((ku == KEY_INF) != (kr == KEY_INF)) set_err(err, ERR_DIST_OVERFLOW);
+            }
         }
-        const bool q = valid && !L->found[j] && ku != KEY_INF && (uint32_t)ku == (uint32_t)kr &&
-                       (ku >> 32) + w == (kr >> 32);
-        const uint64_t mq = __ballot(q);
-        // lanes of row j in this step start at lane sj; the first qualifying one wins
-        const uint32_t sj = ex > base ? ex - base : 0;
-        const uint64_t earlier = mq & ((1ull << ln) - 1ull) & ~((1ull << sj) - 1ull);
-        if (q && earlier == 0) {
-            pred[rj] = u;
-            L->found[j] = 1;
+        if (wp) {
+            const bool q = valid && !L->found[j] && ku != KEY_INF && (uint32_t)ku == (uint32_t)kr &&
+                           (ku >> 32) + w == (kr >> 32);
+            const uint64_t mq = __ballot(q);
+            // lanes of row j in this step start at lane sj; the first qualifying one wins
+            const uint32_t sj = ex > base ? ex - base : 0;
+            const uint64_t earlier = mq & ((1ull << ln) - 1ull) & ~((1ull << sj) - 1ull);
+            if (q && earlier == 0) {
+                pred[rj] = u;
+                L->found[j] = 1;
+            }
         }
-        if (valid && rj < u && ku != KEY_INF) boundary_candidate(pt, err, kr, ku, w, e);
+        if (need && rj < u && ku != KEY_INF && kr != KEY_INF) boundary_candidate(pt, err, kr, ku, w, e);
         wave_sync();
     }
 }
 
+// One wave scans one chunk of a row above scan_heavy: boundary candidates and
+// the row's first qualifying offset (atomicMin into heavy_pe).  An unreached
+// row only checks its edges a -> b, a < b, for the overflow test (without
+// pred; with pred every reached row checks all of its own entries).
 DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *pt, uint32_t *err,
                            uint32_t *heavy_pe, uint32_t lc) {
     // heavy row h owning chunk lc: largest h with heavy_chunk_off[h] <= lc
@@ -896,10 +998,20 @@ DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *p
     const uint32_t h = lo, row = S.g.heavy_rows[h];
     const uint32_t c = lc - S.g.heavy_chunk_off[h];
     const uint64_t kv = key[row];
-    if (kv == KEY_INF) return;
+    if (kv == KEY_INF && S.with_pred) return;
     const uint32_t beg = S.g.rp[row] + c * S.g.scan_chunk;
     const uint32_t lim = S.g.rp[row + 1];
     const uint32_t end = (lim - beg > S.g.scan_chunk) ? beg + S.g.scan_chunk : lim;
+    if (kv == KEY_INF) {
+        for (uint32_t e0 = beg; e0 < end; e0 += 64) {
+            const uint32_t e = e0 + lane();
+            if (e < end) {
+                const uint32_t u = S.g.adj[e].x;
+                if (row < u && key[u] != KEY_INF) set_err(err, ERR_DIST_OVERFLOW);
+            }
+        }
+        return;
+    }
     const bool is_seed = (kv >> 32) == 0;
     uint32_t best = NONE;
     for (uint32_t e0 = beg; e0 < end; e0 += 64) {
@@ -997,9 +1109,9 @@ __global__ void __launch_bounds__(256) k_compact(CompactParams C) {
 
 // Alg. 2 Steps 5-6 on the pred forest: the tree is every chosen cross-cell
 // edge plus, from both of its endpoints, every edge (x, pred(x)) up to the
-// cell's seed.  Walks only mark the vertices they pass (one dependent load
-// per step, no read-back); one pass over the marks then writes each marked
-// vertex's edge once, which is the set semantics of E_S, and clears the mark.
+// cell's seed.  Walks claim the vertices they pass and find their preds; one
+// pass over the marks then writes each claimed vertex's edge once, which is
+// the set semantics of E_S, and clears the marks.
 
 DEVI void emit_edges(const ExpandParams &E, bool on, uint32_t x, uint32_t y, uint32_t w) {
     const uint64_t m = __ballot(on);
@@ -1015,9 +1127,85 @@ DEVI void emit_edges(const ExpandParams &E, bool on, uint32_t x, uint32_t y, uin
     }
 }
 
-// Two threads per chosen edge: thread 2q finds the row u of edge e (binary
-// search over rp), writes (u, v, w) and walks from u; thread 2q+1 walks from v.
+// Row of CSR offset e: the largest r with rp[r] <= e, by a 64-way search
+// (each step probes 64 offsets, one per lane).  Wave-uniform result.
+DEVI uint32_t wave_row_of(const DevGraph &g, uint32_t e) {
+    uint32_t lo = 0, hi = g.n;  // rp[lo] <= e < rp[hi]
+    while (hi - lo > 1) {
+        const uint32_t span = hi - lo;
+        const uint32_t probe = lo + (uint32_t)(((uint64_t)span * lane()) >> 6);
+        const bool ok = lane() == 0 || g.rp[probe] <= e;
+        const uint64_t m = __ballot(ok);
+        const uint32_t jm = 63u - (uint32_t)__clzll((long long)m);
+        const uint32_t nlo = __shfl(probe, (int)jm, 64);
+        const uint32_t nhi = jm == 63 ? hi : __shfl(probe, (int)jm + 1, 64);
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
+// pred of reached non-seed vertex x (key kx): rows above scan_heavy have it
+// from the scan; smaller rows are scanned here, 64 entries per step, for the
+// first entry (smallest neighbour, then smallest offset) of the same cell on
+// a shortest path.  Wave-uniform result, NONE if there is none.
+DEVI uint32_t wave_pred_of(const ExpandParams &E, uint32_t x, uint64_t kx) {
+    const uint32_t beg = E.g.rp[x], deg = E.g.rp[x + 1] - beg;
+    if (deg > E.g.scan_heavy) return E.pred[x];
+    for (uint32_t c = 0; c < deg; c += 64) {
+        const uint32_t i = c + lane();
+        bool q = false;
+        uint32_t u = 0;
+        if (i < deg) {
+            const uint2 a = E.g.adj[beg + i];
+            u = a.x;
+            const uint64_t ku = E.key[u];
+            q = ku != KEY_INF && (uint32_t)ku == (uint32_t)kx && (ku >> 32) + a.y == (kx >> 32);
+        }
+        const uint64_t m = __ballot(q);
+        if (m) return __shfl(u, __ffsll((unsigned long long)m) - 1, 64);
+    }
+    return NONE;
+}
+
+// One wave per walk: walk 2q starts at the row end of chosen edge q (and
+// writes that edge), walk 2q+1 at its column end.  A walk claims each vertex
+// it reaches (a byte of mark); the first walk to claim a vertex finds its
+// pred and goes on, a later one stops there, since the rest of the path is
+// the same.  Claimed vertices get their pred in E.pred.
 __global__ void __launch_bounds__(256) k_expand_walk(ExpandParams E) {
+    const uint32_t wid = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const uint32_t q = wid >> 1, end = wid & 1u, n = E.g.n;
+    const bool live = q < *E.nsel;
+    uint32_t x = 0, v = 0, w = 0;
+    if (live) {
+        const uint32_t e = E.sel_e[q];
+        const uint2 a = E.g.adj[e];
+        v = a.x;
+        w = a.y;
+        x = end == 0 ? wave_row_of(E.g, e) : a.x;
+    }
+    emit_edges(E, live && end == 0 && lane() == 0, x, v, w);
+    if (!live) return;
+    for (uint32_t steps = 0; steps < n; steps++) {
+        const uint64_t kx = E.key[x];
+        if ((kx >> 32) == 0 || kx == KEY_INF) break;  // the seed (an unreached vertex cannot occur)
+        const uint32_t bit = 1u << (8 * (x & 3u));
+        uint32_t old = 0;
+        if (lane() == 0) old = atomicOr(E.mark + (x >> 2), bit);
+        old = __shfl(old, 0, 64);
+        if (old & bit) break;  // another walk goes on from here
+        const uint32_t p = wave_pred_of(E, x, kx);
+        if (lane() == 0) E.pred[x] = p;
+        if (p >= n) break;  // cannot happen for a converged pass; the emit pass skips x
+        x = p;
+    }
+}
+
+// With every pred known: two threads per chosen edge, thread 2q starting at
+// the row end (and writing the edge), 2q+1 at the column end; a walk only
+// sets the marks of the vertices it passes (one dependent load per step).
+__global__ void __launch_bounds__(256) k_expand_walk_ready(ExpandParams E) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t q = t >> 1, end = t & 1u, n = E.g.n;
     const bool live = q < *E.nsel;
@@ -1057,11 +1245,12 @@ __global__ void __launch_bounds__(256) k_expand_emit(ExpandParams E) {
         if (word) E.mark[t] = 0u;
         for (uint32_t b = 0; b < 4; b++) {
             const uint32_t x = 4 * t + b;
-            const bool on = ((word >> (8 * b)) & 0xFFu) != 0;
+            bool on = ((word >> (8 * b)) & 0xFFu) != 0;
             uint32_t p = 0, w = 0;
             if (on) {
                 p = E.pred[x];
-                w = (uint32_t)((E.key[x] >> 32) - (E.key[p] >> 32));
+                on = p < n;
+                if (on) w = (uint32_t)((E.key[x] >> 32) - (E.key[p] >> 32));
             }
             emit_edges(E, on, x, p, w);
         }
@@ -1264,9 +1453,12 @@ hipError_t launch_compact(const CompactParams &C, uint32_t grid, uint32_t block,
 }
 
 hipError_t launch_expand(const ExpandParams &E, uint32_t emit_grid, hipStream_t s) {
-    if (E.nsel_max) {
-        const uint64_t threads = 2ull * E.nsel_max;
-        hipLaunchKernelGGL(k_expand_walk, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, E);
+    if (E.nsel_max && E.pred_ready) {
+        const uint64_t threads = 2ull * E.nsel_max;  // one thread per walk
+        hipLaunchKernelGGL(k_expand_walk_ready, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, E);
+    } else if (E.nsel_max) {
+        const uint64_t waves = 2ull * E.nsel_max;  // one wave per walk, four per workgroup
+        hipLaunchKernelGGL(k_expand_walk, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, E);
     }
     hipLaunchKernelGGL(k_expand_emit, dim3(emit_grid), dim3(256), 0, s, E);
     return hipGetLastError();

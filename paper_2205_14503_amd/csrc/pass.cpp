@@ -44,6 +44,7 @@ void bind_state(VorParams &P, const Options &o, uint64_t cap_s, uint64_t cap_b) 
     P.local_iters = o.local_iters;
     P.counting = o.counting ? 1u : 0u;
     P.split = (o.delta != 0xFFFFFFFFu && o.split) ? 1u : 0u;
+    P.lq_mode = o.lq_mode;
 }
 
 namespace {
@@ -104,8 +105,8 @@ void TailScratch::release() {
     mark_n = 0;
 }
 
-int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, const uint32_t *pred, uint32_t k,
-                 const uint64_t *pt, const uint32_t *g1_idx, uint32_t m, TailScratch &ts,
+int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
+                 const uint64_t *pt, const uint32_t *g1_idx, uint32_t m, bool pred_ready, TailScratch &ts,
                  std::unique_ptr<steiner_result> &out, double *ms_mst, double *ms_expand) {
     const uint32_t n = g->n;
     int rc;
@@ -134,14 +135,16 @@ int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, const ui
     EP.ob = EP.oa + n;
     EP.ow = EP.oa + 2 * (size_t)n;
     EP.ocnt = M.hdr + 3;
+    EP.pred_ready = pred_ready ? 1u : 0u;
     const uint32_t emit_grid = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>((uint64_t)std::max(1, g->cu_count) * 8, (((uint64_t)n + 3) / 4 + 255) / 256));
     // Step 3 (MST of G'1), Step 4 (its kept cross-cell edges), Steps 5-6 (pred walks)
-    rc = hip_check(hipEventRecord(ts.ev[0], st), "event");
+    const bool timed = ms_mst || ms_expand;
+    rc = timed ? hip_check(hipEventRecord(ts.ev[0], st), "event") : STEINER_OK;
     if (!rc) rc = hip_check(launch_mst(M, g1_idx, m, st), "mst");
-    if (!rc) rc = hip_check(hipEventRecord(ts.ev[1], st), "event");
+    if (!rc && timed) rc = hip_check(hipEventRecord(ts.ev[1], st), "event");
     if (!rc) rc = hip_check(launch_expand(EP, emit_grid, st), "expand");
-    if (!rc) rc = hip_check(hipEventRecord(ts.ev[2], st), "event");
+    if (!rc && timed) rc = hip_check(hipEventRecord(ts.ev[2], st), "event");
     uint32_t *h = ts.host.as<uint32_t>();
     if (!rc) rc = hip_check(hipMemcpyAsync(h, M.hdr, 16, hipMemcpyDeviceToHost, st), "D2H counts");
     if (!rc) rc = hip_check(hipStreamSynchronize(st), "tail sync");
@@ -155,11 +158,13 @@ int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, const ui
         ts.mark_n = 0;
         return fail(STEINER_EDEVICE, "tree expansion overflow (%u MST edges, %u tree edges)", nsel, m_out);
     }
-    float t_mst = 0.f, t_exp = 0.f;
-    (void)hipEventElapsedTime(&t_mst, ts.ev[0], ts.ev[1]);
-    (void)hipEventElapsedTime(&t_exp, ts.ev[1], ts.ev[2]);
-    if (ms_mst) *ms_mst += t_mst;
-    if (ms_expand) *ms_expand += t_exp;
+    if (timed) {
+        float t_mst = 0.f, t_exp = 0.f;
+        (void)hipEventElapsedTime(&t_mst, ts.ev[0], ts.ev[1]);
+        (void)hipEventElapsedTime(&t_exp, ts.ev[1], ts.ev[2]);
+        if (ms_mst) *ms_mst += t_mst;
+        if (ms_expand) *ms_expand += t_exp;
+    }
     std::vector<uint32_t> a(m_out), b(m_out), w(m_out);
     rc = hip_check(hipMemcpyAsync(a.data(), EP.oa, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
     if (!rc) rc = hip_check(hipMemcpyAsync(b.data(), EP.ob, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
@@ -300,15 +305,17 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
 
     // ------------------------------------------------- Step 1: Voronoi cells
     PassCtl *hpass = (PassCtl *)(hctl + L.pass);
-    // per-launch event pairs of the relaxation kernels (timing mode only)
-    std::vector<hipEvent_t> kev;
+    // event pairs around each chunk of relaxation launches (timing mode only);
+    // the gaps between the launches of a chunk count as kernel time
+    size_t nkev = 0;
     auto kmark = [&]() {
         if (!o.timing) return;
-        hipEvent_t e;
-        if (hipEventCreate(&e) == hipSuccess) {
-            (void)hipEventRecord(e, st);
-            kev.push_back(e);
+        if (nkev == ws.events.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            ws.events.push_back(e);
         }
+        (void)hipEventRecord(ws.events[nkev++], st);
     };
     uint32_t relax_launches = 0;
     const uint32_t round_cap = 1u << 26;
@@ -343,13 +350,13 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     } else {
         uint32_t chunk_rounds = 4, launched = 0;
         for (;;) {
+            kmark();
             for (uint32_t i = 0; i < chunk_rounds; i++) {
-                kmark();
                 rc = hip_check(launch_round(P, o.grid, o.block, st), "round");
-                kmark();
                 relax_launches++;
                 if (rc) return rc;
             }
+            kmark();
             launched += chunk_rounds;
             if ((rc = hip_check(hipMemcpyAsync(hpass, P.pass, sizeof(PassCtl), hipMemcpyDeviceToHost, st), "D2H pass")))
                 return rc;
@@ -363,12 +370,11 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     }
     const uint32_t rounds = hpass->round;
     double ms_relax = 0.0;
-    for (size_t i = 0; i + 1 < kev.size(); i += 2) {
+    for (size_t i = 0; i + 1 < nkev; i += 2) {
         float m = 0.f;
-        (void)hipEventSynchronize(kev[i + 1]);
-        if (hipEventElapsedTime(&m, kev[i], kev[i + 1]) == hipSuccess) ms_relax += m;
+        (void)hipEventSynchronize(ws.events[i + 1]);
+        if (hipEventElapsedTime(&m, ws.events[i], ws.events[i + 1]) == hipSuccess) ms_relax += m;
     }
-    for (hipEvent_t e : kev) (void)hipEventDestroy(e);
     tm.mark();  // 2
 
     // ------------------------------ canonical pred + Step 2 boundary scan
@@ -381,6 +387,9 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     SP.slot_ids = (const uint32_t *)(ctl + L.slot_ids);
     SP.nscan = Q;
     SP.slot_err = (uint32_t *)(ctl + L.slot_err);
+    SP.with_pred = o.lazy_pred ? 0 : 1;
+    for (uint32_t a : act)
+        if (qs[a].want_key) SP.with_pred = 1;
     const uint32_t sgrid = (uint32_t)std::max(1, g->cu_count) * 8;
     if ((rc = hip_check(launch_scan(SP, sgrid, 256, st), "scan"))) return rc;
     tm.mark();  // 3
@@ -450,7 +459,8 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
             continue;
         }
         int trc = tree_from_g1(g, st, P.key + (size_t)s * n, P.aux + (size_t)s * n, k, ws.pt.as<uint64_t>() + pt_off[s],
-                               ws.cidx.as<uint32_t>() + oc_off[s], m, ws.tail, qq.result, &ms_mst, &ms_expand);
+                               ws.cidx.as<uint32_t>() + oc_off[s], m, SP.with_pred != 0, ws.tail, qq.result,
+                               o.timing ? &ms_mst : nullptr, o.timing ? &ms_expand : nullptr);
         if (trc == STEINER_EDISCONNECTED) {
             qq.status = trc;
             continue;

@@ -270,6 +270,7 @@ void steiner_server::run_tail() {
         SP.slot_ids = ids + slot;
         SP.nscan = 1;
         SP.slot_err = (uint32_t *)(c + L.slot_err);
+        SP.with_pred = o.lazy_pred ? 0 : 1;
         CompactParams CP{};
         CP.pt = SP.pt;
         CP.pt_len = (const uint64_t *)(c + L.pt_len);
@@ -298,7 +299,7 @@ void steiner_server::run_tail() {
                 uint8_t *base = pool.as<uint8_t>() + r->pool_off;
                 const uint32_t *oi = (const uint32_t *)(base + ((8 * P_ + 255) & ~255ull));
                 status = tree_from_g1(g, s_tail, P.key + (size_t)slot * n, P.aux + (size_t)slot * n, k,
-                                      (const uint64_t *)base, oi, cnt, tail, res, nullptr, nullptr);
+                                      (const uint64_t *)base, oi, cnt, SP.with_pred != 0, tail, res, nullptr, nullptr);
                 if (!status) res->stats.pairs = cnt;
             }
         }

@@ -1,0 +1,32 @@
+"""Compile-time properties of the relaxation kernel that its launch
+configuration relies on (no GPU needed): the default grid assumes five
+256-thread workgroups per CU, so the round kernel must fit five waves per
+SIMD without scratch spills."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2205_14503_amd", "csrc")
+HIPCC = "/opt/rocm/bin/hipcc"
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not installed")
+def test_round_kernel_occupancy(tmp_path):
+    cmd = [HIPCC, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-I" + os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, "kernels.hip"),
+           "-o", str(tmp_path / "k.o"), "-Rpass-analysis=kernel-resource-usage"]
+    out = subprocess.run(cmd, capture_output=True, text=True, check=True).stderr
+    blocks = re.split(r"remark: Function Name: ", out)
+    info = {}
+    for b in blocks[1:]:
+        name = b.split()[0]
+        fields = dict(re.findall(r"remark:\s+([A-Za-z \[\]/]+?):\s+(\d+)", b))
+        info[name] = fields
+    rnd = next(v for k, v in info.items() if "k_round" in k)
+    assert int(rnd["Occupancy [waves/SIMD]"]) >= 5, rnd
+    assert int(rnd["ScratchSize [bytes/lane]"]) == 0, rnd
+    scan = next(v for k, v in info.items() if k.startswith("_ZN3stn6k_scan"))
+    assert int(scan["Occupancy [waves/SIMD]"]) >= 8, scan
