@@ -73,18 +73,22 @@ def _pmc_per_kernel(path: str):
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
+def _config_key(delta, local, split=False) -> str:
+    return f"delta={int(delta)},local_iters={int(local)},split={int(bool(split))}"
+
+
 def pmc_summary(args):
-    """profiles/traffic.json entry + a text summary from two counter runs of
-    bench.py (FETCH_SIZE, WRITE_SIZE) and two of the copy calibration."""
+    """Entry of profiles/traffic.json (workload -> relaxation options -> bytes)
+    and a text table, from two counter runs of bench.py (FETCH_SIZE,
+    WRITE_SIZE) and two of the copy calibration."""
     fetch, write, cfetch, cwrite = args.pmc_summary
     copy_kib = 1 << 20  # the calibration copies 1 GiB
     f_scale = copy_kib / _pmc_per_kernel(cfetch)["__amd_rocclr_copyBuffer"][0]
     w_scale = copy_kib / _pmc_per_kernel(cwrite)["__amd_rocclr_copyBuffer"][0]
     fk, wk = _pmc_per_kernel(fetch), _pmc_per_kernel(write)
-    entry = {"kernel_sha": kernel_sha(), "kernel": "k_round",
-             "config": {"delta": args.delta or None, "local_iters": args.local or None},
-             "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4), "per_kernel": {}}
-    lines = ["| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | scaled MB/dispatch |",
+    entry = {"kernel_sha": kernel_sha(), "kernel": "k_round", "fetch_scale": round(f_scale, 4),
+             "write_scale": round(w_scale, 4), "per_kernel": {}}
+    lines = ["| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | HBM MB/dispatch (scaled) |",
              "|---|---|---|---|---|"]
     for name in sorted(fk, key=lambda x: -fk[x][0] * fk[x][1]):
         fv, cnt = fk[name]
@@ -92,15 +96,45 @@ def pmc_summary(args):
         mb = (fv * f_scale + wv * w_scale) * 1024 / 1e6
         entry["per_kernel"][name] = {"dispatches": cnt, "fetch_kib": round(fv, 3), "write_kib": round(wv, 3),
                                      "bytes": round(mb * 1e6)}
-        lines.append(f"| {name} | {cnt} | {fv:.1f} | {wv:.1f} | {mb:.3f} |")
+        if cnt and mb > 0.01:
+            lines.append(f"| {name} | {cnt} | {fv:.1f} | {wv:.1f} | {mb:.3f} |")
     entry["bytes_per_launch"] = entry["per_kernel"]["k_round"]["bytes"]
     data = json.load(open(TRAFFIC_FILE)) if os.path.exists(TRAFFIC_FILE) else {}
-    data[args.workload] = entry
+    data.setdefault(args.workload, {})[_config_key(args.delta, args.local)] = entry
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
-    print(f"calibration: copy of 1 GiB reads {copy_kib / f_scale:.1f} KiB FETCH_SIZE (x{f_scale:.4f}), "
-          f"writes {copy_kib / w_scale:.1f} KiB WRITE_SIZE (x{w_scale:.4f})")
+    print(f"Copy calibration: a 1 GiB device copy reads {copy_kib / f_scale:.1f} KiB of FETCH_SIZE "
+          f"(scale x{f_scale:.4f}) and writes {copy_kib / w_scale:.1f} KiB of WRITE_SIZE (scale x{w_scale:.4f}).\n")
     print("\n".join(lines))
+
+
+def trace_summary(args):
+    """Per-kernel durations over the timed region of one bench.py run under
+    rocprofv3 --kernel-trace (its JSON line gives steps and relaxation
+    launches per step; the region starts at the first of the last
+    steps x launches relaxation dispatches)."""
+    import csv
+    trace_csv, json_file = args.trace_summary
+    line = json.loads([x for x in open(json_file) if x.startswith("{")][-1])
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    nk = int(round(line["steps"] * line["roofline"]["launches_per_step"]))
+    kr = [i for i, r in enumerate(rows) if r["Kernel_Name"].startswith("stn::k_round")]
+    first = kr[-nk]
+    acc = {}
+    for r in rows[first:]:
+        name = r["Kernel_Name"].split("(")[0]
+        acc.setdefault(name, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in acc.values())
+    print(f"Timed region: {line['steps']} steps of {line['config']['workload']}, "
+          f"{line['ms_per_step']} ms per step, value {line['value']} {line['unit']}.\n")
+    print("| kernel | calls | avg us | total ms per step | share of GPU time |\n|---|---|---|---|---|")
+    for name, v in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+        print(f"| {name} | {len(v)} | {sum(v) / len(v):.2f} | {sum(v) / line['steps'] / 1e3:.4f} | "
+              f"{100 * sum(v) / total:.2f}% |")
+    rf = line["roofline"]
+    ka = acc["stn::k_round"]
+    print(f"\nk_round: rocprofv3 average {sum(ka) / len(ka):.2f} us per launch; bench.py HIP-event average "
+          f"{rf['avg_launch_us']} us per launch (event pairs around chunks of launches, gaps included).")
 
 
 def bench_batch(args, st, W, np, torch, stream):
@@ -219,10 +253,16 @@ def main():
     ap.add_argument("--local", type=int, default=0, help="local-queue depth (with --delta: skips the tuner)")
     ap.add_argument("--copy-calib", action="store_true", help="run only the copy kernel used to scale HBM counters")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
-                    help="write the workload's entry of profiles/traffic.json from rocprofv3 counter runs")
+                    help="write the workload's entry of profiles/traffic.json from rocprofv3 counter runs "
+                         "(with the --delta and --local those runs used)")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
+                    help="per-kernel durations over the timed region of a bench.py run under rocprofv3")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args)
+        return
+    if args.trace_summary:
+        trace_summary(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
@@ -307,12 +347,11 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
-            tf = json.load(open(TRAFFIC_FILE))
-            ent = tf.get(args.workload)
-            used = {"delta": opts.get("delta", tuned and tuned["delta"]),
-                    "local_iters": opts.get("local_iters", tuned and tuned["local_iters"])}
-            used = {key: (int(val) if val else None) for key, val in used.items()}
-            if ent and ent.get("kernel_sha") == kernel_sha() and ent.get("config") == used:
+            delta = opts.get("delta", tuned and tuned["delta"])
+            local = opts.get("local_iters", tuned and tuned["local_iters"])
+            split = bool(tuned and tuned["split"])
+            ent = json.load(open(TRAFFIC_FILE)).get(args.workload, {}).get(_config_key(delta, local, split))
+            if ent and ent.get("kernel_sha") == kernel_sha():
                 traffic = ent["bytes_per_launch"]
         except Exception:
             traffic = None

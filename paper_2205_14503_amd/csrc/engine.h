@@ -1,6 +1,7 @@
 // Host-side engine internals (not part of the public ABI).
 #pragma once
 #include <memory>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -140,9 +141,12 @@ struct steiner_graph {
     uint32_t tuned_local = 0;
     uint32_t tuned_split = 0;
     uint32_t tuned_pred = 0;     // 0: untuned, 1: eager, 2: lazy
+    uint32_t last_rounds = 0;    // relaxation rounds of the previous pass (sizes the first launch chunk)
     double avg_w = 1.0;
     int cu_count = 256;
     std::mutex mu;               // serialises solves on this graph
+    mutable std::mutex memo_mu;  // guards chunk_memo
+    mutable std::map<uint64_t, uint64_t> chunk_memo;  // (small_max << 32 | chunk) -> chunks of rows above small_max
     stn::Workspace ws;
 };
 

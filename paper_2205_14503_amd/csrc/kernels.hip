@@ -1075,32 +1075,52 @@ __global__ void k_scan_heavy_pred(ScanParams S) {
 
 // --------------------------------------------------------- G'1 compaction
 
+// G'1 extraction: the finite entries of each query's pair table, as (pair
+// index, value).  A workgroup takes tiles of 1024 entries (each lane four,
+// coalesced) and reserves its output slots with one atomic per tile.
 __global__ void __launch_bounds__(256) k_compact(CompactParams C) {
-    const uint32_t wpb = blockDim.x / 64, w = threadIdx.x / 64;
-    const uint64_t wave_gid = (uint64_t)blockIdx.x * wpb + w, nwaves = (uint64_t)gridDim.x * wpb;
+    __shared__ uint32_t s_wave_sum[4];
+    __shared__ uint32_t s_base;
+    const uint32_t wv = threadIdx.x / 64;
     for (uint32_t si = 0; si < C.nscan; si++) {
         const uint32_t slot = C.slot_ids[si];
         const uint64_t *pt = C.pt[slot];
         const uint64_t len = C.pt_len[slot];
-        for (uint64_t base = wave_gid * 64; base < len; base += nwaves * 64) {
-            const uint64_t i = base + lane();
-            const uint64_t val = i < len ? pt[i] : KEY_INF;
-            const bool keep = val != KEY_INF;
-            const uint64_t m = __ballot(keep);
-            if (m == 0) continue;
-            const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1;
-            uint32_t pos0 = 0;
-            if (lane() == leader) pos0 = atomicAdd(&C.out_cnt[slot], (uint32_t)__popcll(m));
-            pos0 = __shfl(pos0, leader, 64);
-            if (keep) {
-                const uint32_t pos = pos0 + lanes_below(m);
-                if (pos < C.out_cap[slot]) {
-                    C.out_idx[slot][pos] = (uint32_t)i;
-                    C.out_val[slot][pos] = val;
-                } else {
-                    atomicOr(&C.pass->err, ERR_LIST_OVERFLOW);
+        const uint64_t tiles = (len + 1023) / 1024;
+        for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {  // uniform per workgroup
+            uint64_t val[4];
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint64_t i = tile * 1024 + (uint64_t)j * 256 + threadIdx.x;
+                val[j] = i < len ? pt[i] : KEY_INF;
+                cnt += val[j] != KEY_INF;
+            }
+            const uint32_t incl = wave_incl_scan(cnt);
+            if (lane() == 63) s_wave_sum[wv] = incl;
+            __syncthreads();
+            uint32_t before = 0, total = 0;
+            for (uint32_t i = 0; i < blockDim.x / 64; i++) {
+                if (i < wv) before += s_wave_sum[i];
+                total += s_wave_sum[i];
+            }
+            if (threadIdx.x == 0 && total) s_base = atomicAdd(&C.out_cnt[slot], total);
+            __syncthreads();
+            if (cnt) {
+                uint32_t pos = s_base + before + incl - cnt;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (val[j] == KEY_INF) continue;
+                    if (pos < C.out_cap[slot]) {
+                        C.out_idx[slot][pos] = (uint32_t)(tile * 1024 + (uint64_t)j * 256 + threadIdx.x);
+                        C.out_val[slot][pos] = val[j];
+                    } else {
+                        atomicOr(&C.pass->err, ERR_LIST_OVERFLOW);
+                    }
+                    pos++;
                 }
             }
+            __syncthreads();
         }
     }
 }
@@ -1235,25 +1255,60 @@ __global__ void __launch_bounds__(256) k_expand_walk_ready(ExpandParams E) {
     }
 }
 
+// Writes the edge (x, pred x) of every marked vertex and clears the marks.
+// Each thread covers one 4-vertex mark word; a workgroup reserves the output
+// slots of its whole tile with one atomic.
 __global__ void __launch_bounds__(256) k_expand_emit(ExpandParams E) {
+    __shared__ uint32_t s_wave_sum[4];
+    __shared__ uint32_t s_base;
     const uint32_t n = E.g.n, words = (n + 3) / 4;
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < words; base += stride) {
+    const uint32_t wv = threadIdx.x / 64;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < words; base += stride) {  // uniform trip count
         const uint32_t t = base + threadIdx.x;
         const uint32_t word = t < words ? E.mark[t] : 0u;
-        if (__ballot(word != 0) == 0) continue;
-        if (word) E.mark[t] = 0u;
-        for (uint32_t b = 0; b < 4; b++) {
-            const uint32_t x = 4 * t + b;
-            bool on = ((word >> (8 * b)) & 0xFFu) != 0;
-            uint32_t p = 0, w = 0;
-            if (on) {
-                p = E.pred[x];
-                on = p < n;
-                if (on) w = (uint32_t)((E.key[x] >> 32) - (E.key[p] >> 32));
+        uint32_t px[4], wx[4], cnt = 0;
+        if (word) {
+            E.mark[t] = 0u;
+#pragma unroll
+            for (uint32_t b = 0; b < 4; b++) {
+                px[b] = NONE;
+                if ((word >> (8 * b)) & 0xFFu) {
+                    const uint32_t x = 4 * t + b;
+                    const uint32_t p = E.pred[x];
+                    if (p < n) {
+                        px[b] = p;
+                        wx[b] = (uint32_t)((E.key[x] >> 32) - (E.key[p] >> 32));
+                        cnt++;
+                    }
+                }
             }
-            emit_edges(E, on, x, p, w);
         }
+        const uint32_t incl = wave_incl_scan(cnt);
+        if (lane() == 63) s_wave_sum[wv] = incl;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (uint32_t i = 0; i < blockDim.x / 64; i++) {
+            if (i < wv) before += s_wave_sum[i];
+            total += s_wave_sum[i];
+        }
+        if (threadIdx.x == 0 && total) s_base = atomicAdd(E.ocnt, total);
+        __syncthreads();
+        if (cnt) {
+            uint32_t pos = s_base + before + incl - cnt;
+#pragma unroll
+            for (uint32_t b = 0; b < 4; b++) {
+                if (!((word >> (8 * b)) & 0xFFu) || px[b] >= n) continue;
+                const uint32_t x = 4 * t + b;
+                if (pos < n) {
+                    E.oa[pos] = min(x, px[b]);
+                    E.ob[pos] = max(x, px[b]);
+                    E.ow[pos] = wx[b];
+                }
+                pos++;
+            }
+        }
+        __syncthreads();  // s_wave_sum and s_base are reused by the next tile
     }
 }
 
@@ -1334,8 +1389,7 @@ __global__ void __launch_bounds__(256) k_mst_edges(MstParams M, uint32_t in) {
 // only the smaller records it and only the larger hooks.  With distinct keys
 // those 2-cycles are the only cycles, so pointer jumping flattens the hooks
 // into trees, every seed then takes its new root, and the minima are reset.
-__global__ void __launch_bounds__(1024) k_mst_merge(MstParams M, uint32_t in) {
-    __shared__ int s_changed;
+DEVI void mst_merge_body(const MstParams &M, int *s_changed) {
     const uint32_t k = M.k;
     for (uint32_t c = threadIdx.x; c < k; c += blockDim.x) {
         uint32_t h = c;
@@ -1357,23 +1411,82 @@ __global__ void __launch_bounds__(1024) k_mst_merge(MstParams M, uint32_t in) {
     }
     __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) s_changed = 0;
+        if (threadIdx.x == 0) *s_changed = 0;
         __syncthreads();
         for (uint32_t c = threadIdx.x; c < k; c += blockDim.x) {
             const uint32_t h = M.hook[c], hh = M.hook[h];
             if (hh != h) {
                 M.hook[c] = hh;
-                s_changed = 1;
+                *s_changed = 1;
             }
         }
         __syncthreads();
-        const int changed = s_changed;
+        const int changed = *s_changed;
         __syncthreads();
         if (!changed) break;
     }
     for (uint32_t c = threadIdx.x; c < k; c += blockDim.x) M.par[c] = M.hook[M.par[c]];
     for (uint32_t c = threadIdx.x; c < k; c += blockDim.x) M.best[c] = ~0ull;
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) k_mst_merge(MstParams M, uint32_t in) {
+    __shared__ int s_changed;
+    mst_merge_body(M, &s_changed);
     if (threadIdx.x == 0) M.hdr[in] = 0;
+}
+
+// The whole Borůvka in one workgroup, for a small G'1: the same steps as
+// k_mst_edges + k_mst_merge per round, with the list counts in LDS.
+__global__ void __launch_bounds__(1024) k_mst_small(MstParams M, const uint32_t *g1_idx, uint32_t m, uint32_t rounds) {
+    __shared__ uint32_t s_cnt[2];
+    __shared__ int s_changed;
+    for (uint32_t c = threadIdx.x; c < M.k; c += blockDim.x) {
+        M.par[c] = c;
+        M.best[c] = ~0ull;
+    }
+    if (threadIdx.x == 0) {
+        s_cnt[0] = m;
+        s_cnt[1] = 0;
+        M.hdr[0] = M.hdr[1] = M.hdr[2] = M.hdr[3] = 0;
+    }
+    __syncthreads();
+    uint32_t in = 0;
+    for (uint32_t r = 0; r <= rounds; r++) {
+        const uint32_t cnt = s_cnt[in], out = in ^ 1u;
+        if (cnt == 0) break;  // uniform: read after a barrier
+        const uint32_t *src = r == 0 ? g1_idx : M.edges[in];
+        for (uint32_t base = 0; base < cnt; base += blockDim.x) {
+            const uint32_t t = base + threadIdx.x;
+            bool live = false;
+            uint32_t p = 0;
+            if (t < cnt) {
+                p = src[t];
+                uint32_t i, j;
+                pair_of(p, &i, &j);
+                const uint32_t ci = M.par[i], cj = M.par[j];
+                if (ci != cj) {
+                    live = true;
+                    const unsigned long long key = ((M.pt[p] >> 32) << 32) | rank_of(i, j, M.k);
+                    if (key < M.best[ci]) atomicMin(M.best + ci, key);
+                    if (key < M.best[cj]) atomicMin(M.best + cj, key);
+                }
+            }
+            const uint64_t mk = __ballot(live);
+            if (mk) {
+                const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mk) - 1;
+                uint32_t pos = 0;
+                if (lane() == leader) pos = atomicAdd(&s_cnt[out], (uint32_t)__popcll(mk));
+                pos = __shfl(pos, leader, 64);
+                if (live) M.edges[out][pos + lanes_below(mk)] = p;
+            }
+        }
+        __syncthreads();
+        mst_merge_body(M, &s_changed);
+        if (threadIdx.x == 0) s_cnt[in] = 0;
+        __syncthreads();
+        in = out;
+    }
 }
 
 // ------------------------------------------------------------ launchers
@@ -1465,11 +1578,15 @@ hipError_t launch_expand(const ExpandParams &E, uint32_t emit_grid, hipStream_t 
 }
 
 hipError_t launch_mst(const MstParams &M, const uint32_t *g1_idx, uint32_t m, hipStream_t s) {
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(2048, ((uint64_t)std::max(m, M.k) + 255) / 256);
-    hipLaunchKernelGGL(k_mst_init, dim3(grid), dim3(256), 0, s, M, g1_idx, m);
     // every round at least halves the number of components that still have an outgoing edge
     uint32_t rounds = 1;
     while ((1ull << rounds) < M.k) rounds++;
+    if (m <= (1u << 16)) {
+        hipLaunchKernelGGL(k_mst_small, dim3(1), dim3(1024), 0, s, M, g1_idx, m, rounds);
+        return hipGetLastError();
+    }
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(2048, ((uint64_t)std::max(m, M.k) + 255) / 256);
+    hipLaunchKernelGGL(k_mst_init, dim3(grid), dim3(256), 0, s, M, g1_idx, m);
     const uint32_t egrid = (uint32_t)std::min<uint64_t>(2048, ((uint64_t)m + 255) / 256 + 1);
     for (uint32_t r = 0; r <= rounds; r++) {
         hipLaunchKernelGGL(k_mst_edges, dim3(egrid), dim3(256), 0, s, M, r & 1u);

@@ -9,12 +9,22 @@
 
 namespace stn {
 
+// Chunks of the rows above small_max (sizes the chunk lists); one O(n) host
+// pass per (small_max, chunk) and graph, remembered.
 uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chunk) {
+    const uint64_t memo_key = ((uint64_t)small_max << 32) | chunk;
+    {
+        std::lock_guard<std::mutex> lk(g->memo_mu);
+        auto it = g->chunk_memo.find(memo_key);
+        if (it != g->chunk_memo.end()) return it->second;
+    }
     uint64_t t = 0;
     for (uint32_t v = 0; v < g->n; v++) {
         uint64_t d = g->h_rp[v + 1] - g->h_rp[v];
         if (d > small_max) t += (d + chunk - 1) / chunk;
     }
+    std::lock_guard<std::mutex> lk(g->memo_mu);
+    g->chunk_memo[memo_key] = t;
     return t;
 }
 
@@ -165,28 +175,52 @@ int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t
         if (ms_mst) *ms_mst += t_mst;
         if (ms_expand) *ms_expand += t_exp;
     }
-    std::vector<uint32_t> a(m_out), b(m_out), w(m_out);
-    rc = hip_check(hipMemcpyAsync(a.data(), EP.oa, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
-    if (!rc) rc = hip_check(hipMemcpyAsync(b.data(), EP.ob, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
-    if (!rc) rc = hip_check(hipMemcpyAsync(w.data(), EP.ow, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+    // the edge arrays into pinned memory, one synchronisation
+    if ((rc = ts.host.ensure(((size_t)m_out * 3 + 16) * 4))) return rc;
+    uint32_t *ha = ts.host.as<uint32_t>() + 16, *hb = ha + m_out, *hw = hb + m_out;
+    rc = hip_check(hipMemcpyAsync(ha, EP.oa, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+    if (!rc) rc = hip_check(hipMemcpyAsync(hb, EP.ob, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+    if (!rc) rc = hip_check(hipMemcpyAsync(hw, EP.ow, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
     if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H edges");
     if (rc) return rc;
-    // Step 7: canonical order (a, b, w) and D
-    std::vector<uint32_t> ord(m_out);
-    for (uint32_t t = 0; t < m_out; t++) ord[t] = t;
-    std::sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) {
-        return a[x] != a[y] ? a[x] < a[y] : b[x] != b[y] ? b[x] < b[y] : w[x] < w[y];
-    });
+    // Step 7: canonical order (a, b, w) and D.  A tree has one edge per vertex
+    // pair, so (a, b) decides the order: LSD radix sort of (a << 32 | b), w
+    // riding along, 11-bit digits within each half, constant digits skipped.
     std::unique_ptr<steiner_result> res(new steiner_result());
+    std::vector<uint64_t> ek(m_out), ek2(m_out);
+    std::vector<uint32_t> val(hw, hw + m_out), val2(m_out);
+    for (uint32_t t = 0; t < m_out; t++) ek[t] = ((uint64_t)ha[t] << 32) | hb[t];
+    std::vector<uint32_t> hist(2048);
+    for (uint32_t pass = 0; pass < 6 && m_out > 1; pass++) {
+        const uint32_t shift = (pass / 3) * 32 + (pass % 3) * 11;
+        const uint32_t width = pass % 3 == 2 ? 10 : 11;
+        const uint64_t mask = (1ull << width) - 1;
+        std::fill(hist.begin(), hist.end(), 0u);
+        for (uint32_t t = 0; t < m_out; t++) hist[(ek[t] >> shift) & mask]++;
+        if (hist[(ek[0] >> shift) & mask] == m_out) continue;  // one digit value: already in order
+        uint32_t sum = 0;
+        for (uint32_t &h : hist) {
+            const uint32_t c = h;
+            h = sum;
+            sum += c;
+        }
+        for (uint32_t t = 0; t < m_out; t++) {
+            const uint32_t at = hist[(ek[t] >> shift) & mask]++;
+            ek2[at] = ek[t];
+            val2[at] = val[t];
+        }
+        ek.swap(ek2);
+        val.swap(val2);
+    }
     res->a.resize(m_out);
     res->b.resize(m_out);
     res->w.resize(m_out);
     uint64_t D = 0;
     for (uint32_t t = 0; t < m_out; t++) {
-        res->a[t] = a[ord[t]];
-        res->b[t] = b[ord[t]];
-        res->w[t] = w[ord[t]];
-        D += res->w[t];
+        res->a[t] = (uint32_t)(ek[t] >> 32);
+        res->b[t] = (uint32_t)ek[t];
+        res->w[t] = val[t];
+        D += val[t];
     }
     res->total = D;
     res->stats.tree_edges = m_out;
@@ -348,7 +382,8 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
                 return fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)", hpass->round);
         }
     } else {
-        uint32_t chunk_rounds = 4, launched = 0;
+        // the first chunk covers as many rounds as the previous pass on this graph needed
+        uint32_t chunk_rounds = std::min<uint32_t>(std::max<uint32_t>(g->last_rounds, 4), 64), launched = 0;
         for (;;) {
             kmark();
             for (uint32_t i = 0; i < chunk_rounds; i++) {
@@ -369,6 +404,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         }
     }
     const uint32_t rounds = hpass->round;
+    g->last_rounds = rounds;
     double ms_relax = 0.0;
     for (size_t i = 0; i + 1 < nkev; i += 2) {
         float m = 0.f;
