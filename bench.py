@@ -137,6 +137,65 @@ def trace_summary(args):
           f"{rf['avg_launch_us']} us per launch (event pairs around chunks of launches, gaps included).")
 
 
+def bench_sweep(args, st, W, np, torch, stream):
+    """The paper's sensitivity studies on one GPU (RMAT scale `--sweep-scale`,
+    edge factor 16): bucket width from Dijkstra-like to unbounded (its
+    priority-queue vs FIFO study), weight ranges [1,100]..[1,100K], seed
+    counts 10..10K and the seed-selection strategies.  Relaxation attempts
+    stand in for the paper's message counts.  Prints a markdown table."""
+    flags = st.FLAG_TIMING | st.FLAG_COUNTERS
+    scale = args.sweep_scale
+    rows = []
+
+    def measure(dg, seeds, opts, **tags):
+        dg.solve(seeds, dict(opts, flags=flags))
+        ts, last = [], None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            last = dg.solve(seeds, dict(opts, flags=flags))
+            ts.append((time.perf_counter() - t0) * 1e3)
+        x = last.stats
+        row = dict(tags, ms=round(float(np.median(ts)), 3), voronoi_ms=round(x["ms_voronoi"], 3),
+                   scan_ms=round(x["ms_scan"], 3), rounds=x["rounds"], messages=x["relax_attempts"],
+                   atomics=x["relax_atomics"], improved=x["relax_improved"], tree_edges=len(last.a), D=last.total)
+        rows.append(row)
+        print(f"[sweep] {row}", file=sys.stderr, flush=True)
+
+    def graph(whi):
+        g = W.rmat(scale, 16, wlo=1, whi=whi)
+        return g, W.lcc(g)
+
+    g, cand = graph(1000)
+    dg = st.Graph(g, 0, stream)
+    seeds = W.sample(cand, 1000, 1, W.STREAM_SEEDS)
+    for delta in (1, 16, 128, 500, 2000, 8000, 0xFFFFFFFF):
+        measure(dg, seeds, {"delta": delta}, study="bucket width", weights="[1,1000]", k=1000,
+                delta="unbounded" if delta == 0xFFFFFFFF else delta)
+    for k in (10, 100, 1000, 10000):
+        s = W.sample(cand, k, 1, W.STREAM_SEEDS)
+        tuned = dg.tune(s)
+        measure(dg, s, {}, study="seed count", weights="[1,1000]", k=k,
+                delta="unbounded (tuned)" if tuned["delta"] == 0xFFFFFFFF else f"{tuned['delta']} (tuned)")
+    for strat in W.SEED_STRATEGIES:
+        s = W.make_seeds(g, 100, cand=cand, strategy=strat)
+        measure(dg, s, {}, study="seed strategy", weights="[1,1000]", k=100, strategy=strat)
+    dg.close()
+    for whi in (100, 10000, 100000):
+        g, cand = graph(whi)
+        dg = st.Graph(g, 0, stream)
+        s = W.sample(cand, 1000, 1, W.STREAM_SEEDS)
+        for delta in (0xFFFFFFFF, max(1, whi // 2)):
+            measure(dg, s, {"delta": delta}, study="weight range", weights=f"[1,{whi}]", k=1000,
+                    delta="unbounded" if delta == 0xFFFFFFFF else delta)
+        dg.close()
+    cols = ["study", "weights", "k", "delta", "strategy", "ms", "voronoi_ms", "scan_ms", "rounds", "messages",
+            "atomics", "improved", "tree_edges", "D"]
+    print(f"RMAT scale {scale}, edge factor 16 ({g.n} vertices), one MI355X; messages = relaxation attempts.\n")
+    print("| " + " | ".join(cols) + " |\n|" + "---|" * len(cols))
+    for r in rows:
+        print("| " + " | ".join(str(r.get(c, "")) for c in cols) + " |")
+
+
 def bench_batch(args, st, W, np, torch, stream):
     """Batched multi-query pass vs one-at-a-time solves (same graph, same queries)."""
     spec = W.WORKLOADS[args.workload]
@@ -251,6 +310,9 @@ def main():
     ap.add_argument("--slots", type=int, default=32, help="serving: resident query slots")
     ap.add_argument("--budget-gb", type=int, default=96, help="serving: device memory budget")
     ap.add_argument("--local", type=int, default=0, help="local-queue depth (with --delta: skips the tuner)")
+    ap.add_argument("--seeds", default="uniform", help="seed strategy: uniform, bfs_level, eccentric, proximate")
+    ap.add_argument("--sweep", action="store_true", help="run the sensitivity studies instead of the benchmark")
+    ap.add_argument("--sweep-scale", type=int, default=22, help="RMAT scale of the sensitivity studies")
     ap.add_argument("--copy-calib", action="store_true", help="run only the copy kernel used to scale HBM counters")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the workload's entry of profiles/traffic.json from rocprofv3 counter runs "
@@ -280,6 +342,9 @@ def main():
         copy_calibration(torch)
         return
     stream = torch.cuda.current_stream()
+    if args.sweep:
+        bench_sweep(args, st, W, np, torch, stream)
+        return
     spec = W.WORKLOADS[args.workload]
     if "queries" in spec:
         print(json.dumps(bench_batch(args, st, W, np, torch, stream)), flush=True)
@@ -290,7 +355,7 @@ def main():
     t0 = time.time()
     g = W.make_graph(args.workload)
     k = spec["k"]
-    seeds = W.make_seeds(g, k)
+    seeds = W.make_seeds(g, k, strategy=args.seeds)
     labels = W.components(g)
     comp = np.isin(labels, np.unique(labels[seeds]))
     nnz_reached = int(g.degrees()[comp].sum())
@@ -390,7 +455,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "k": k, "seed": 1,
+        "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "k": k, "seed": 1, "seeds": args.seeds,
                    "weights": [spec["wlo"], spec["whi"]], "reached_nnz": nnz_reached},
         "queries_per_s": round(1e3 / ms_per_step, 3),
         "p50_ms": round(float(np.percentile(lat, 50)), 4),

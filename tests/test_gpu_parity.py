@@ -217,3 +217,16 @@ def test_batch_equals_single_and_oracle(stream):
                     assert tree.edges == ref.edges and tree.total == ref.total, f"query {q}"
                     single = dg.solve(sets[q], OPTION_SETS[name])
                     assert single.edges == tree.edges
+
+
+def test_seed_strategies(stream):
+    """The paper's seed-selection variants (BFS-level, uniform, eccentric,
+    proximate) give the same trees as the oracle."""
+    g = W.rmat(14, 16, wlo=1, whi=1000)
+    cand = W.lcc(g)
+    gg = W.grid(61, 67, 1, 1000)
+    for strat in W.SEED_STRATEGIES:
+        say(f"rmat14 seeds={strat}")
+        check_case(g, W.make_seeds(g, 40, master=9, cand=cand, strategy=strat), stream, None, f"rmat14 {strat}")
+        say(f"grid 61x67 seeds={strat}")
+        check_case(gg, W.make_seeds(gg, 25, master=9, strategy=strat), stream, None, f"grid {strat}")

@@ -72,3 +72,59 @@ def test_query_sizes_log_uniform():
     assert 0.4 < np.mean(ks < mid) < 0.6
     t = W.poisson_arrivals(1000, rate=50.0)
     assert np.all(np.diff(t) > 0) and 15 < t[-1] < 25
+
+
+def _py_bfs(g, src):
+    from collections import deque
+    lv = [None] * g.n
+    lv[src] = 0
+    q = deque([src])
+    while q:
+        v = q.popleft()
+        for e in range(int(g.row_ptr[v]), int(g.row_ptr[v + 1])):
+            u = int(g.col[e])
+            if lv[u] is None:
+                lv[u] = lv[v] + 1
+                q.append(u)
+    return [0xFFFFFFFF if x is None else x for x in lv]
+
+
+def test_bfs_levels_match_python():
+    for g in (W.er(300, 500, 1, 9, 3), W.grid(13, 17, 1, 5, 4), W.rmat(9, 8, wlo=1, whi=9, master=5)):
+        for src in (0, g.n // 2, g.n - 1):
+            assert W.bfs_levels(g, src).tolist() == _py_bfs(g, src)
+
+
+def test_kbfs_seed_strategies_by_definition():
+    g = W.rmat(9, 8, wlo=1, whi=9, master=6)
+    cand = W.lcc(g)
+    for mode in ("eccentric", "proximate"):
+        s = W.seeds_kbfs(g, 12, mode, master=2, cand=cand)
+        assert len(set(s.tolist())) == 12 and set(s.tolist()) <= set(cand.tolist())
+        acc = {int(v): 0 for v in cand}
+        for i in range(1, 12):  # each further seed extremises the level sum over the seeds before it
+            lv = _py_bfs(g, int(s[i - 1]))
+            for v in acc:
+                acc[v] += lv[v]
+            rest = [v for v in acc if v not in set(int(x) for x in s[:i])]
+            key = (lambda v: (-acc[v], v)) if mode == "eccentric" else (lambda v: (acc[v], v))
+            assert int(s[i]) == min(rest, key=key), (mode, i)
+    gg = W.grid(20, 20, 1, 3, 7)
+    prox = W.seeds_kbfs(gg, 2, "proximate", master=3)
+    assert _py_bfs(gg, int(prox[0]))[int(prox[1])] == 1  # the nearest other vertex is a neighbour
+    ecc = W.seeds_kbfs(gg, 2, "eccentric", master=3)
+    lv = _py_bfs(gg, int(ecc[0]))
+    assert lv[int(ecc[1])] == max(lv)
+
+
+def test_bfs_level_seeds_follow_level_sizes():
+    g = W.grid(40, 50, 1, 9, 8)
+    cand = np.arange(g.n, dtype=np.uint32)
+    s = W.seeds_bfs_level(g, 60, master=4, cand=cand)
+    assert len(s) == 60 and len(set(s.tolist())) == 60
+    root = int(W.sample(cand, 1, 4, W.STREAM_SEEDS)[0])
+    lv = W.bfs_levels(g, root)
+    sizes = np.bincount(lv)
+    got = np.bincount(lv[s], minlength=len(sizes))
+    assert np.all(np.abs(got - sizes * 60 / g.n) < 1.0 + 1e-9)  # largest-remainder quotas
+    assert np.array_equal(W.make_seeds(g, 60, master=4, cand=cand, strategy="bfs_level"), s)

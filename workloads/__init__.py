@@ -79,6 +79,11 @@ def _load():
     lib.wl_sample.restype = ctypes.c_int
     lib.wl_sample.argtypes = [ctypes.c_void_p, u32, u32, u64, ctypes.c_void_p]
     lib.wl_num_threads.restype = ctypes.c_int
+    lib.wl_bfs_levels.restype = None
+    lib.wl_bfs_levels.argtypes = [u32, ctypes.c_void_p, ctypes.c_void_p, u32, ctypes.c_void_p]
+    lib.wl_kbfs_seeds.restype = ctypes.c_int
+    lib.wl_kbfs_seeds.argtypes = [u32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, u32, u32, u32,
+                                  ctypes.c_int, ctypes.c_void_p]
     _lib = lib
     return lib
 
@@ -305,10 +310,70 @@ def seed_candidates(g: Graph) -> np.ndarray:
     return lcc(g)
 
 
-def make_seeds(g: Graph, k: int, master: int = 1, stream: int = STREAM_SEEDS, cand=None) -> np.ndarray:
+def bfs_levels(g: Graph, src: int) -> np.ndarray:
+    """Hop counts from src; 0xFFFFFFFF where unreached."""
+    out = np.empty(g.n, dtype=np.uint32)
+    _load().wl_bfs_levels(g.n, g.row_ptr.ctypes.data, g.col.ctypes.data, int(src), out.ctypes.data)
+    return out
+
+
+SEED_STRATEGIES = ("uniform", "bfs_level", "eccentric", "proximate")
+
+
+def seeds_bfs_level(g: Graph, k: int, master: int = 1, stream: int = STREAM_SEEDS, cand=None) -> np.ndarray:
+    """The paper's default seed selection (Section V): BFS levels of the
+    candidates from a random root, then a uniform sample from every level
+    with quotas proportional to the level sizes (largest remainder), level l
+    drawing from stream `stream * 1000 + 1 + l`."""
     if cand is None:
         cand = seed_candidates(g)
-    return sample(cand, k, master, stream)
+    cand = np.ascontiguousarray(cand, dtype=np.uint32)
+    if k > len(cand):
+        raise ValueError("k exceeds the candidate count")
+    root = int(sample(cand, 1, master, stream)[0])
+    lv = bfs_levels(g, root)[cand]
+    levels, counts = np.unique(lv, return_counts=True)
+    exact = counts * (k / len(cand))
+    quota = np.floor(exact).astype(np.int64)
+    order = np.lexsort((levels, -(exact - quota)))
+    quota[order[:k - int(quota.sum())]] += 1
+    out = []
+    for l, q in zip(levels, quota):
+        if q:
+            out.append(sample(cand[lv == l], int(q), master, stream * 1000 + 1 + int(l)))
+    return np.concatenate(out).astype(np.uint32)
+
+
+def seeds_kbfs(g: Graph, k: int, mode: str, master: int = 1, stream: int = STREAM_SEEDS, cand=None) -> np.ndarray:
+    """"eccentric" (seeds far apart) or "proximate" (seeds close together):
+    the paper's k-BFS seed selection (Section V); the first seed is a uniform
+    draw from the candidates, which must lie in one component.  One BFS per
+    seed, so meant for modest k."""
+    if cand is None:
+        cand = seed_candidates(g)
+    cand = np.ascontiguousarray(cand, dtype=np.uint32)
+    first = int(sample(cand, 1, master, stream)[0])
+    out = np.empty(k, dtype=np.uint32)
+    m = {"eccentric": 0, "proximate": 1}[mode]
+    if _load().wl_kbfs_seeds(g.n, g.row_ptr.ctypes.data, g.col.ctypes.data, cand.ctypes.data, len(cand), first, k, m,
+                             out.ctypes.data) != 0:
+        raise ValueError("k exceeds the candidate count")
+    return out
+
+
+def make_seeds(g: Graph, k: int, master: int = 1, stream: int = STREAM_SEEDS, cand=None,
+               strategy: str = "uniform") -> np.ndarray:
+    """k seeds of graph g by one of SEED_STRATEGIES (uniform from the seed
+    candidates unless asked otherwise)."""
+    if cand is None:
+        cand = seed_candidates(g)
+    if strategy == "uniform":
+        return sample(cand, k, master, stream)
+    if strategy == "bfs_level":
+        return seeds_bfs_level(g, k, master, stream, cand)
+    if strategy in ("eccentric", "proximate"):
+        return seeds_kbfs(g, k, strategy, master, stream, cand)
+    raise ValueError(f"unknown seed strategy {strategy!r}")
 
 
 def make_query_set(g: Graph, count: int, k_lo: int, k_hi: int, master: int = 1, cand=None):

@@ -331,3 +331,63 @@ int wl_sample(const uint32_t *cand, uint32_t nc, uint32_t k, uint64_t key, uint3
 }
 
 int wl_num_threads(void) { return omp_get_max_threads(); }
+
+/* Hop counts from src (breadth-first levels); UINT32_MAX where unreached. */
+void wl_bfs_levels(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, uint32_t src, uint32_t *level) {
+    for (uint32_t v = 0; v < n; v++) level[v] = UINT32_MAX;
+    if (src >= n) return;
+    uint32_t *queue = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    uint64_t head = 0, tail = 0;
+    level[src] = 0;
+    queue[tail++] = src;
+    while (head < tail) {
+        uint32_t v = queue[head++];
+        for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            uint32_t u = col[e];
+            if (level[u] == UINT32_MAX) {
+                level[u] = level[v] + 1;
+                queue[tail++] = u;
+            }
+        }
+    }
+    free(queue);
+}
+
+/* Seeds by the k-BFS heuristic of the paper's seed-selection study
+ * (Section V): the first seed is `first`; each further seed is the candidate
+ * not yet chosen whose sum of BFS levels from all seeds chosen so far is the
+ * largest (mode 0, "eccentric": seeds far apart) or the smallest (mode 1,
+ * "proximate": seeds close together); ties go to the smaller vertex id.
+ * cand must lie in one connected component.  Returns 0, or -1 if k > nc. */
+int wl_kbfs_seeds(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, const uint32_t *cand, uint32_t nc,
+                  uint32_t first, uint32_t k, int mode, uint32_t *out) {
+    if (k > nc) return -1;
+    if (k == 0) return 0;
+    uint64_t *acc = (uint64_t *)calloc((size_t)nc, sizeof(uint64_t));
+    uint8_t *chosen = (uint8_t *)calloc((size_t)nc, 1);
+    uint32_t *level = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    uint32_t cur = first;
+    for (uint32_t i = 0; i < nc; i++)
+        if (cand[i] == first) chosen[i] = 1;
+    out[0] = first;
+    for (uint32_t s = 1; s < k; s++) {
+        wl_bfs_levels(n, row_ptr, col, cur, level);
+        int64_t best = -1;
+        for (uint32_t i = 0; i < nc; i++) {
+            acc[i] += level[cand[i]];
+            if (chosen[i]) continue;
+            if (best < 0) { best = i; continue; }
+            const uint64_t a = acc[i], b = acc[best];
+            const int better = mode == 0 ? (a > b || (a == b && cand[i] < cand[best]))
+                                         : (a < b || (a == b && cand[i] < cand[best]));
+            if (better) best = i;
+        }
+        chosen[best] = 1;
+        cur = cand[best];
+        out[s] = cur;
+    }
+    free(acc);
+    free(chosen);
+    free(level);
+    return 0;
+}
