@@ -150,10 +150,16 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
     if (r.block > 256) r.block = 256;  // per-wave LDS scratch of the relaxation kernels (~10 KB per wave)
     if (r.chunk < 64) r.chunk = 64;
     while ((g->max_deg + r.chunk - 1) / r.chunk >= (1ull << CHUNK_BITS)) r.chunk *= 2;  // chunk index field
-    // host-stepped: five 256-thread workgroups per CU, the occupancy the relaxation kernel's registers allow;
+    // host-stepped: as many workgroups as are resident at once (the round kernel's occupancy);
     // persistent: two per CU at most, the co-residency its grid barrier needs
-    if (r.grid == 0)
-        r.grid = (uint32_t)std::max(1, g->cu_count) * (r.driver == 2 ? 2u * (1024u / r.block) : 5u * (256u / r.block));
+    if (r.grid == 0) {
+        if (r.driver == 2) {
+            r.grid = (uint32_t)std::max(1, g->cu_count) * 2u * (1024u / r.block);
+        } else {
+            const int resident = round_max_grid(r.block);
+            r.grid = resident > 0 ? (uint32_t)resident : (uint32_t)std::max(1, g->cu_count) * 4u;
+        }
+    }
     return r;
 }
 

@@ -58,6 +58,8 @@ hipError_t launch_round(const VorParams &P, uint32_t grid, uint32_t block, hipSt
 hipError_t launch_persistent(const VorParams &P, uint32_t grid, uint32_t block, uint32_t max_rounds,
                              hipStream_t s);
 int persistent_max_grid(uint32_t block);
+// Workgroups of the round kernel that fit on the device at once (0 if unknown).
+int round_max_grid(uint32_t block);
 
 hipError_t launch_scan(const ScanParams &S, uint32_t grid, uint32_t block, hipStream_t s);
 hipError_t launch_compact(const CompactParams &C, uint32_t grid, uint32_t block, hipStream_t s);

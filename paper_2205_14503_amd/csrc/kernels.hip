@@ -193,39 +193,46 @@ DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr
     WaveScratch *L = use_lq ? Lw : nullptr;
     const uint32_t n = P.g.n;
     uint64_t cand[UNROLL], cur[UNROLL];
-    bool live[UNROLL], improved[UNROLL];
+    uint32_t tv[UNROLL];  // bucket end, clamped: every stored distance is below 2^32 - 1
+    bool live[UNROLL], tried[UNROLL], near[UNROLL];
+    // All loads and atomics of the UNROLL steps are issued unconditionally (idle lanes read vertex 0
+    // of their slot) and the atomics return nothing, so that they are in flight together; a branch
+    // around an access, or a returned value, makes the compiler wait for it before the next one.
 #pragma unroll
     for (int i = 0; i < UNROLL; i++) {
         const uint64_t d = (ksrc[i] >> 32) + (uint64_t)w[i];
         live[i] = valid[i] && d < DIST_INF;  // a distance of 2^32-1 or more is never stored
         cand[i] = (d << 32) | (ksrc[i] & 0xFFFFFFFFull);
+        tv[i] = (uint32_t)min(thr[slot[i]], (uint64_t)DIST_INF);
     }
 #pragma unroll
     for (int i = 0; i < UNROLL; i++)  // possibly stale (larger) values: filter only
-        cur[i] = live[i] ? P.key[(size_t)slot[i] * n + u[i]] : 0;
-#pragma unroll
-    for (int i = 0; i < UNROLL; i++) {
-        count(P, Lw, EV_ATTEMPT, valid[i]);
-        count(P, Lw, EV_ATOMIC, live[i] && cand[i] < cur[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < UNROLL; i++) {
-        improved[i] = false;
-        if (live[i] && cand[i] < cur[i]) {
-            const uint64_t old = atomicMin((unsigned long long *)(P.key + (size_t)slot[i] * n + u[i]),
-                                           (unsigned long long)cand[i]);
-            improved[i] = cand[i] < old;
-        }
-    }
-    bool near[UNROLL];
+        cur[i] = P.key[(size_t)slot[i] * n + (live[i] ? u[i] : 0u)];
+    // A lane whose candidate beats its (possibly stale) read treats the edge as an improvement: the
+    // lane whose atomic really lowers the key is always among them, and the others only add an
+    // expansion that finds nothing, so no atomic has to return its old value.
     uint32_t beg[UNROLL], deg[UNROLL];
 #pragma unroll
     for (int i = 0; i < UNROLL; i++) {
+        tried[i] = live[i] && cand[i] < cur[i];
+        near[i] = tried[i] && (uint32_t)(cand[i] >> 32) < tv[i];
+        const uint32_t r = near[i] ? u[i] : 0u;
+        beg[i] = P.g.rp[r];
+        deg[i] = P.g.rp[r + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        count(P, Lw, EV_ATTEMPT, valid[i]);
+        count(P, Lw, EV_ATOMIC, tried[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++)
+        if (tried[i]) (void)atomicMin((unsigned long long *)(P.key + (size_t)slot[i] * n + u[i]), (unsigned long long)cand[i]);
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
         const uint32_t nd = (uint32_t)(cand[i] >> 32);
-        near[i] = improved[i] && (uint64_t)nd < thr[slot[i]];
-        beg[i] = near[i] ? P.g.rp[u[i]] : 0;
-        deg[i] = near[i] ? P.g.rp[u[i] + 1] : 0;
-        if (improved[i] && !near[i]) {  // park until the query's bucket reaches it
+        if (!near[i]) beg[i] = deg[i] = 0;
+        if (tried[i] && !near[i]) {  // park until the query's bucket reaches it
             P.dirty[(size_t)slot[i] * n + u[i]] = 1;
             uint32_t *fm = P.far_min + (size_t)R.b * P.nslots + slot[i];
             if (nd < *fm) atomicMin(fm, nd);
@@ -252,9 +259,9 @@ DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr
                 lq_tail += min((uint32_t)__popcll(m), space);
             }
         }
-        count(P, Lw, EV_IMPROVED, improved[i]);
+        count(P, Lw, EV_IMPROVED, tried[i]);
         count(P, Lw, EV_LOCAL, local);
-        count(P, Lw, EV_PARK, improved[i] && !near[i]);
+        count(P, Lw, EV_PARK, tried[i] && !near[i]);
         bool claim = false;
         if (near[i] && !local) {
             if (atomicExch(P.aux + (size_t)slot[i] * n + u[i], R.r + 1) != R.r + 1) {
@@ -316,9 +323,9 @@ DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *th
             hv[i] = L->pad[j] != 0;
         }
 #pragma unroll
-        for (int i = 0; i < UNROLL; i++) {
-            const uint2 a = valid[i] ? P.g.adj[e[i]] : make_uint2(0, 0);
-            uu[i] = a.x;
+        for (int i = 0; i < UNROLL; i++) {  // unconditional loads (idle lanes read entry 0): all in flight together
+            const uint2 a = P.g.adj[valid[i] ? e[i] : 0u];
+            uu[i] = valid[i] ? a.x : 0u;
             ww[i] = a.y;
             if (P.split) valid[i] = valid[i] && (hv[i] ? a.y > P.delta : a.y <= P.delta);
         }
@@ -354,8 +361,8 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
         for (int i = 0; i < UNROLL; i++) {
             const uint64_t e = (uint64_t)e0 + 64 * i + lane();
             valid[i] = e < end;
-            const uint2 a = valid[i] ? P.g.adj[e] : make_uint2(0, 0);
-            uu[i] = a.x;
+            const uint2 a = P.g.adj[valid[i] ? e : (uint64_t)beg];
+            uu[i] = valid[i] ? a.x : 0u;
             ww[i] = a.y;
             if (P.split) valid[i] = valid[i] && (heavy ? a.y > P.delta : a.y <= P.delta);
             sl[i] = slot;
@@ -607,9 +614,9 @@ DEVI void advance_body(const VorParams &P, const uint64_t *thr, const uint64_t *
 // One round per launch: the advance scan decided at the end of the previous
 // round (its pushes are processed one round later), the relaxation of this
 // round's list, and, in the last workgroup to finish, the bucket decision.
-// 256-thread workgroups (the host clamps the block size); at most 96 VGPRs,
-// so that five waves per SIMD fit (the default grid assumes five workgroups per CU).
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_round(VorParams P) {
+// 256-thread workgroups (the host clamps the block size); the default grid is
+// as many workgroups as fit on the device at once (round_max_grid).
+__global__ void __launch_bounds__(256) k_round(VorParams P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     WaveScratch *s_wave = (WaveScratch *)dyn_smem;
     __shared__ int s_last, s_adv, s_act;
@@ -1532,6 +1539,15 @@ static size_t wave_smem(uint32_t block) { return (size_t)(block / 64) * sizeof(W
 hipError_t launch_round(const VorParams &P, uint32_t grid, uint32_t block, hipStream_t s) {
     hipLaunchKernelGGL(k_round, dim3(grid), dim3(block), wave_smem(block), s, P);
     return hipGetLastError();
+}
+
+int round_max_grid(uint32_t block) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round, (int)block, wave_smem(block)) != hipSuccess)
+        return 0;
+    return per_cu * prop.multiProcessorCount;
 }
 
 int persistent_max_grid(uint32_t block) {
