@@ -288,6 +288,9 @@ WORKLOADS = {
                            k_lo=3, k_hi=4096, seeds_from="lcc"),
     "rmat24_serve": dict(kind="rmat", scale=24, edgefactor=16, wlo=1, whi=1000, k_lo=3, k_hi=10000,
                          seeds_from="lcc"),
+    # batching where one query leaves the GPU mostly idle (high diameter: latency bound)
+    "grid2048_batch32": dict(kind="grid", rows=2048, cols=2048, wlo=1, whi=1000, queries=32, k_lo=10, k_hi=1000,
+                             seeds_from="all"),
 }
 
 
