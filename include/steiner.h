@@ -68,7 +68,8 @@ typedef struct steiner_server steiner_server; /* continuous-batching query serve
 typedef struct steiner_options {
     uint32_t delta;       /* bucket width of the distance-ordered relaxation; 0 = default for the graph,
                              0xFFFFFFFF = one unbounded bucket (plain label correcting) */
-    uint32_t driver;      /* 0 = default, 1 = host-stepped rounds, 2 = one persistent cooperative kernel */
+    uint32_t driver;      /* 0 = default, 1 = host-stepped rounds, 2 = one persistent cooperative kernel,
+                             3 = cluster-local relaxation in LDS (single queries; batches use 1) */
     uint32_t block;       /* threads per workgroup (multiple of 64, <= 1024); 0 = default */
     uint32_t grid;        /* workgroups of the relaxation pass; 0 = default */
     uint32_t small_max;   /* rows up to this degree are expanded wave-cooperatively; 0 = default */

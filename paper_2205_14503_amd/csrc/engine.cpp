@@ -389,6 +389,7 @@ extern "C" int steiner_graph_free(steiner_graph *g) {
     (void)hipSetDevice(g->device);
     (void)hipStreamSynchronize(g->stream);
     g->ws.release();
+    g->clusters.release();
     dev_free(g->d_rp);
     dev_free(g->d_adj);
     dev_free(g->d_heavy_rows);

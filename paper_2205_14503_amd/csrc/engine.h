@@ -123,6 +123,21 @@ struct steiner_result {
     steiner_stats stats{};
 };
 
+namespace stn {
+// BFS-grown vertex clusters of the cluster-local driver (built on first use).
+struct ClusterSet {
+    bool built = false;
+    uint32_t nclusters = 0;
+    DevBuf members, cstart, cl_of, irp, erp, ie, ee, expanded, lists, stamp, ctl;
+    int build(steiner_graph *g);
+    void release() {
+        DevBuf *all[] = {&members, &cstart, &cl_of, &irp, &erp, &ie, &ee, &expanded, &lists, &stamp, &ctl};
+        for (DevBuf *b : all) b->release();
+        built = false;
+    }
+};
+}  // namespace stn
+
 struct steiner_graph {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -148,6 +163,7 @@ struct steiner_graph {
     mutable std::mutex memo_mu;  // guards chunk_memo
     mutable std::map<uint64_t, uint64_t> chunk_memo;  // (small_max << 32 | chunk) -> chunks of rows above small_max
     stn::Workspace ws;
+    stn::ClusterSet clusters;
 };
 
 namespace stn {

@@ -82,4 +82,37 @@ struct MstParams {
 };
 hipError_t launch_mst(const MstParams &M, const uint32_t *g1_idx, uint32_t m, hipStream_t s);
 
+// Cluster-local relaxation of one query (Alg. 2 Step 1; driver 3): the
+// vertices form BFS-grown clusters of at most CLUSTER_MAX vertices; a
+// workgroup relaxes an active cluster's internal edges in LDS to local
+// convergence, then its external edges with global atomics.
+constexpr uint32_t CLUSTER_MAX = 1024;    // vertices per cluster
+constexpr uint32_t CLUSTER_EDGES = 4096;  // edge entries of a cluster's members (staged in LDS)
+struct ClusterCtl {
+    uint32_t cnt[3];       // list lengths, rotating by round mod 3
+    uint32_t round;
+    uint32_t done;
+    uint32_t blocks_done;
+    uint32_t err;
+    uint32_t pad;
+};
+struct ClusterParams {
+    uint32_t n, nclusters;
+    const uint32_t *members;  // [n] vertices grouped by cluster
+    const uint32_t *cstart;   // [nclusters + 1] cluster c = members[cstart[c], cstart[c+1])
+    const uint32_t *cl_of;    // [n] cluster of each vertex
+    const uint32_t *irp;      // [n + 1] internal edges of member position p: ie[irp[p], irp[p+1])
+    const uint2 *ie;          // (local index of the target, w)
+    const uint32_t *erp;      // [n + 1] external edges of member position p: ee[erp[p], erp[p+1])
+    const uint2 *ee;          // (target vertex, w)
+    uint64_t *key;            // the query's keys
+    uint64_t *expanded;       // [n] key with which each vertex's edges were last relaxed
+    uint32_t *list[2];        // [nclusters] each: clusters active in the current / next round
+    uint32_t *stamp;          // [nclusters] last round a cluster was listed for, plus one
+    ClusterCtl *ctl;
+};
+hipError_t launch_cluster_start(const ClusterParams &C, const uint32_t *seeds, uint32_t k, hipStream_t s);
+hipError_t launch_cluster_round(const ClusterParams &C, uint32_t grid, hipStream_t s);
+int cluster_max_grid();
+
 }  // namespace stn

@@ -1496,6 +1496,133 @@ __global__ void __launch_bounds__(1024) k_mst_small(MstParams M, const uint32_t 
     }
 }
 
+// ------------------------------------------- cluster-local relaxation
+// One query (driver 3).  A vertex is active in an activation of its cluster
+// when its key is below the key its edges were last relaxed with
+// (expanded).  The workgroup copies the cluster's keys into LDS, relaxes the
+// internal edges of active members sweep by sweep (LDS 64-bit atomicMin; a
+// member improved in a sweep is active in the next) until a sweep improves
+// nothing, writes the keys back with atomicMin, relaxes the external edges of
+// every member it touched with its final key (global atomicMin; a target
+// that improves gets its cluster listed once for the next round) and records
+// the keys as expanded.  The fixed point is the same unique one: a key that
+// drops, from inside or outside, always gets all of its edges relaxed again.
+
+__global__ void k_cluster_start(ClusterParams C, const uint32_t *seeds, uint32_t k) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        const uint32_t c = C.cl_of[seeds[i]];
+        if (atomicExch(C.stamp + c, 1u) != 1u) {
+            const uint32_t pos = atomicAdd(&C.ctl->cnt[0], 1u);
+            if (pos < C.nclusters) C.list[0][pos] = c;
+            else atomicOr(&C.ctl->err, 1u);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cluster_round(ClusterParams C) {
+    __shared__ uint64_t lkey[CLUSTER_MAX];
+    __shared__ uint2 ladj[CLUSTER_EDGES];          // the cluster's internal edges (local target, w)
+    __shared__ uint16_t lrp[CLUSTER_MAX + 1];      // member i's internal edges: ladj[lrp[i], lrp[i+1])
+    __shared__ uint8_t act[2][CLUSTER_MAX];
+    __shared__ uint8_t touched[CLUSTER_MAX];
+    __shared__ int s_changed[2];
+    __shared__ int s_last;
+    if (ld_agent(&C.ctl->done)) return;
+    const uint32_t r = ld_agent(&C.ctl->round);
+    const uint32_t cur = r & 1u, nxt = cur ^ 1u;
+    const uint32_t ncur = min(ld_agent(&C.ctl->cnt[r % 3u]), C.nclusters);
+    uint32_t *cnt_next = &C.ctl->cnt[(r + 1) % 3u];
+    const uint32_t tag = r + 2;  // stamp of a listing for round r + 1
+    for (uint32_t it = blockIdx.x; it < ncur; it += gridDim.x) {
+        const uint32_t c = C.list[cur][it];
+        const uint32_t b = C.cstart[c], m = min(C.cstart[c + 1] - b, CLUSTER_MAX);
+        const uint32_t e0 = C.irp[b], ne = min(C.irp[b + m] - e0, CLUSTER_EDGES);
+        for (uint32_t j = threadIdx.x; j < ne; j += blockDim.x) ladj[j] = C.ie[e0 + j];
+        for (uint32_t i = threadIdx.x; i <= m; i += blockDim.x) lrp[i] = (uint16_t)min(C.irp[b + i] - e0, ne);
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            const uint32_t v = C.members[b + i];
+            const uint64_t kv = ld_agent(C.key + v);
+            lkey[i] = kv;
+            const uint8_t a0 = kv < C.expanded[v] ? 1 : 0;
+            act[0][i] = a0;
+            act[1][i] = 0;
+            touched[i] = a0;
+        }
+        if (threadIdx.x == 0) s_changed[0] = s_changed[1] = 0;
+        __syncthreads();
+        uint32_t a = 0;
+        for (uint32_t sweep = 0; sweep <= m; sweep++) {  // Bellman-Ford on m vertices settles within m sweeps
+            for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+                if (!act[a][i]) continue;
+                act[a][i] = 0;
+                const uint64_t kv = lkey[i];
+                const uint64_t dv = kv >> 32;
+                for (uint32_t e = lrp[i]; e < lrp[i + 1]; e++) {
+                    const uint2 ed = ladj[e];
+                    const uint64_t d = dv + ed.y;
+                    if (d >= DIST_INF) continue;
+                    const uint64_t cand = (d << 32) | (kv & 0xFFFFFFFFull);
+                    if (cand < lkey[ed.x]) {
+                        const uint64_t old = atomicMin((unsigned long long *)&lkey[ed.x], (unsigned long long)cand);
+                        if (cand < old) {
+                            act[a ^ 1u][ed.x] = 1;
+                            touched[ed.x] = 1;
+                            s_changed[a] = 1;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const int changed = s_changed[a];
+            __syncthreads();
+            if (threadIdx.x == 0) s_changed[a] = 0;  // reused two sweeps later, after further barriers
+            if (!changed) break;
+            a ^= 1u;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            if (!touched[i]) continue;
+            const uint32_t v = C.members[b + i];
+            const uint64_t kv = lkey[i];
+            if (kv < ld_agent(C.key + v)) (void)atomicMin((unsigned long long *)(C.key + v), (unsigned long long)kv);
+            const uint64_t dv = kv >> 32;
+            const uint32_t p = b + i;
+            for (uint32_t e = C.erp[p]; e < C.erp[p + 1]; e++) {
+                const uint2 ed = C.ee[e];
+                const uint64_t d = dv + ed.y;
+                if (d >= DIST_INF) continue;
+                const uint64_t cand = (d << 32) | (kv & 0xFFFFFFFFull);
+                if (cand < C.key[ed.x]) {
+                    const uint64_t old = atomicMin((unsigned long long *)(C.key + ed.x), (unsigned long long)cand);
+                    if (cand < old) {
+                        const uint32_t cu = C.cl_of[ed.x];
+                        if (atomicExch(C.stamp + cu, tag) != tag) {
+                            const uint32_t pos = atomicAdd(cnt_next, 1u);
+                            if (pos < C.nclusters) C.list[nxt][pos] = cu;
+                            else atomicOr(&C.ctl->err, 1u);
+                        }
+                    }
+                }
+            }
+            C.expanded[v] = kv;
+        }
+        __syncthreads();  // LDS is reused by the next cluster
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(&C.ctl->blocks_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last || threadIdx.x != 0) return;
+    __threadfence();
+    C.ctl->cnt[(r + 2) % 3u] = 0;
+    C.ctl->blocks_done = 0;
+    if (ld_agent(cnt_next) == 0) C.ctl->done = 1;
+    C.ctl->round = r + 1;
+    __threadfence();
+}
+
 // ------------------------------------------------------------ launchers
 
 static uint32_t fill_grid(uint64_t count) {
@@ -1539,6 +1666,24 @@ static size_t wave_smem(uint32_t block) { return (size_t)(block / 64) * sizeof(W
 hipError_t launch_round(const VorParams &P, uint32_t grid, uint32_t block, hipStream_t s) {
     hipLaunchKernelGGL(k_round, dim3(grid), dim3(block), wave_smem(block), s, P);
     return hipGetLastError();
+}
+
+hipError_t launch_cluster_start(const ClusterParams &C, const uint32_t *seeds, uint32_t k, hipStream_t s) {
+    hipLaunchKernelGGL(k_cluster_start, dim3((k + 255) / 256 + 1), dim3(256), 0, s, C, seeds, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_cluster_round(const ClusterParams &C, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_cluster_round, dim3(grid), dim3(256), 0, s, C);
+    return hipGetLastError();
+}
+
+int cluster_max_grid() {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cluster_round, 256, 0) != hipSuccess) return 0;
+    return per_cu * prop.multiProcessorCount;
 }
 
 int round_max_grid(uint32_t block) {

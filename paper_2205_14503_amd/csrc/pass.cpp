@@ -85,6 +85,84 @@ struct Timer {
 
 }  // namespace
 
+// From each vertex not yet clustered, in id order, a breadth-first search
+// over unclustered vertices collects up to CLUSTER_MAX vertices holding at
+// most CLUSTER_EDGES edge entries (a vertex with more is a cluster of its
+// own); each member's edges are then split into internal ones (target's local
+// index; self-loops dropped, they never improve a key) and external ones
+// (target vertex).
+int ClusterSet::build(steiner_graph *g) {
+    if (built) return STEINER_OK;
+    const uint32_t n = g->n;
+    const uint64_t nnz = g->nnz;
+    hipStream_t st = g->stream;
+    int rc;
+    std::vector<uint2> adj(nnz);
+    if (nnz && (rc = hip_check(hipMemcpyAsync(adj.data(), g->d_adj, nnz * 8, hipMemcpyDeviceToHost, st), "D2H adjacency")))
+        return rc;
+    if ((rc = hip_check(hipStreamSynchronize(st), "D2H adjacency"))) return rc;
+    const std::vector<uint64_t> &rp = g->h_rp;
+    std::vector<uint32_t> cl(n, NONE), loc(n), mem, cs;
+    mem.reserve(n);
+    cs.push_back(0);
+    for (uint32_t s0 = 0; s0 < n; s0++) {
+        if (cl[s0] != NONE) continue;
+        const uint32_t c = (uint32_t)cs.size() - 1, base = (uint32_t)mem.size();
+        uint64_t edges = rp[s0 + 1] - rp[s0];
+        cl[s0] = c;
+        loc[s0] = 0;
+        mem.push_back(s0);
+        for (size_t head = base; head < mem.size() && mem.size() - base < CLUSTER_MAX; head++) {
+            const uint32_t v = mem[head];
+            for (uint64_t e = rp[v]; e < rp[v + 1] && mem.size() - base < CLUSTER_MAX; e++) {
+                const uint32_t u = adj[e].x;
+                const uint64_t du = rp[u + 1] - rp[u];
+                if (cl[u] != NONE || edges + du > CLUSTER_EDGES) continue;
+                cl[u] = c;
+                loc[u] = (uint32_t)(mem.size() - base);
+                mem.push_back(u);
+                edges += du;
+            }
+        }
+        cs.push_back((uint32_t)mem.size());
+    }
+    nclusters = (uint32_t)cs.size() - 1;
+    std::vector<uint32_t> irp_h((size_t)n + 1, 0), erp_h((size_t)n + 1, 0);
+    std::vector<uint2> ie_h, ee_h;
+    ie_h.reserve(nnz);
+    for (uint32_t p = 0; p < n; p++) {
+        const uint32_t v = mem[p];
+        for (uint64_t e = rp[v]; e < rp[v + 1]; e++) {
+            const uint32_t u = adj[e].x;
+            if (u == v) continue;
+            if (cl[u] == cl[v]) ie_h.push_back(make_uint2(loc[u], adj[e].y));
+            else ee_h.push_back(make_uint2(u, adj[e].y));
+        }
+        irp_h[p + 1] = (uint32_t)ie_h.size();
+        erp_h[p + 1] = (uint32_t)ee_h.size();
+    }
+    if ((rc = members.ensure((size_t)n * 4 + 4)) || (rc = cstart.ensure(cs.size() * 4)) ||
+        (rc = cl_of.ensure((size_t)n * 4 + 4)) || (rc = irp.ensure(irp_h.size() * 4)) ||
+        (rc = erp.ensure(erp_h.size() * 4)) || (rc = ie.ensure(ie_h.size() * 8 + 8)) ||
+        (rc = ee.ensure(ee_h.size() * 8 + 8)) || (rc = expanded.ensure((size_t)n * 8 + 8)) ||
+        (rc = lists.ensure((size_t)nclusters * 8 + 8)) || (rc = stamp.ensure((size_t)nclusters * 4 + 4)) ||
+        (rc = ctl.ensure(sizeof(ClusterCtl))))
+        return rc;
+    rc = hip_check(hipMemcpyAsync(members.ptr, mem.data(), (size_t)n * 4, hipMemcpyHostToDevice, st), "H2D clusters");
+    if (!rc) rc = hip_check(hipMemcpyAsync(cstart.ptr, cs.data(), cs.size() * 4, hipMemcpyHostToDevice, st), "H2D clusters");
+    if (!rc) rc = hip_check(hipMemcpyAsync(cl_of.ptr, cl.data(), (size_t)n * 4, hipMemcpyHostToDevice, st), "H2D clusters");
+    if (!rc) rc = hip_check(hipMemcpyAsync(irp.ptr, irp_h.data(), irp_h.size() * 4, hipMemcpyHostToDevice, st), "H2D clusters");
+    if (!rc) rc = hip_check(hipMemcpyAsync(erp.ptr, erp_h.data(), erp_h.size() * 4, hipMemcpyHostToDevice, st), "H2D clusters");
+    if (!rc && !ie_h.empty())
+        rc = hip_check(hipMemcpyAsync(ie.ptr, ie_h.data(), ie_h.size() * 8, hipMemcpyHostToDevice, st), "H2D clusters");
+    if (!rc && !ee_h.empty())
+        rc = hip_check(hipMemcpyAsync(ee.ptr, ee_h.data(), ee_h.size() * 8, hipMemcpyHostToDevice, st), "H2D clusters");
+    if (!rc) rc = hip_check(hipStreamSynchronize(st), "H2D clusters");
+    if (rc) return rc;
+    built = true;
+    return STEINER_OK;
+}
+
 int TailScratch::prepare(uint32_t n, uint32_t k, uint64_t m, hipStream_t st) {
     int rc;
     const size_t k4 = ((size_t)k * 4 + 255) & ~(size_t)255, m4 = ((size_t)m * 4 + 255) & ~(size_t)255;
@@ -358,7 +436,59 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     auto wall = [&]() {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     };
-    bool persistent = o.driver == 2 && Q <= 256;
+    // cluster-local relaxation (one query): rounds over clusters instead of frontier lists
+    const bool clustered = o.driver == 3 && Q == 1;
+    uint32_t cluster_rounds = 0;
+    if (clustered) {
+        ClusterSet &cs = g->clusters;
+        if ((rc = cs.build(g))) return rc;
+        ClusterParams C{};
+        C.n = n;
+        C.nclusters = cs.nclusters;
+        C.members = cs.members.as<uint32_t>();
+        C.cstart = cs.cstart.as<uint32_t>();
+        C.cl_of = cs.cl_of.as<uint32_t>();
+        C.irp = cs.irp.as<uint32_t>();
+        C.ie = cs.ie.as<uint2>();
+        C.erp = cs.erp.as<uint32_t>();
+        C.ee = cs.ee.as<uint2>();
+        C.key = P.key;
+        C.expanded = cs.expanded.as<uint64_t>();
+        C.list[0] = cs.lists.as<uint32_t>();
+        C.list[1] = cs.lists.as<uint32_t>() + cs.nclusters;
+        C.stamp = cs.stamp.as<uint32_t>();
+        C.ctl = cs.ctl.as<ClusterCtl>();
+        rc = hip_check(launch_fill_u64(C.expanded, n, KEY_INF, st), "cluster reset");
+        if (!rc) rc = hip_check(launch_fill_u32(C.stamp, cs.nclusters, 0u, st), "cluster reset");
+        if (!rc) rc = hip_check(launch_fill_u32((uint32_t *)C.ctl, sizeof(ClusterCtl) / 4, 0u, st), "cluster reset");
+        if (!rc) rc = hip_check(launch_cluster_start(C, ws.seeds.as<uint32_t>(), (uint32_t)qs[act[0]].S.size(), st),
+                                "cluster start");
+        if (rc) return rc;
+        const uint32_t cgrid = (uint32_t)std::max(1, cluster_max_grid());
+        ClusterCtl *hc = (ClusterCtl *)(hctl + L.pass);  // pinned scratch; the frontier pass control is unused here
+        uint32_t chunk_rounds = std::min<uint32_t>(std::max<uint32_t>(g->last_rounds, 4), 64), launched = 0;
+        for (;;) {
+            kmark();
+            for (uint32_t i = 0; i < chunk_rounds; i++) {
+                rc = hip_check(launch_cluster_round(C, cgrid, st), "cluster round");
+                relax_launches++;
+                if (rc) return rc;
+            }
+            kmark();
+            launched += chunk_rounds;
+            if ((rc = hip_check(hipMemcpyAsync(hc, C.ctl, sizeof(ClusterCtl), hipMemcpyDeviceToHost, st), "D2H clusters")))
+                return rc;
+            if ((rc = hip_check(hipStreamSynchronize(st), "cluster sync"))) return rc;
+            if (hc->err) return fail(STEINER_EDEVICE, "cluster list overflow");
+            if (hc->done) break;
+            if (launched >= round_cap || wall() > wall_cap_s)
+                return fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)", hc->round);
+            chunk_rounds = std::min<uint32_t>(chunk_rounds * 2, 64);
+        }
+        cluster_rounds = hc->round;
+        hpass->round = 0;  // the frontier pass did not run
+    }
+    bool persistent = !clustered && o.driver == 2 && Q <= 256;
     uint32_t pgrid = 0;
     if (persistent) {
         int mg = persistent_max_grid(o.block);
@@ -381,7 +511,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
             if (hpass->round >= round_cap || wall() > wall_cap_s)
                 return fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)", hpass->round);
         }
-    } else {
+    } else if (!clustered) {
         // the first chunk covers as many rounds as the previous pass on this graph needed
         uint32_t chunk_rounds = std::min<uint32_t>(std::max<uint32_t>(g->last_rounds, 4), 64), launched = 0;
         for (;;) {
@@ -403,7 +533,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
             chunk_rounds = std::min<uint32_t>(chunk_rounds * 2, 64);
         }
     }
-    const uint32_t rounds = hpass->round;
+    const uint32_t rounds = clustered ? cluster_rounds : hpass->round;
     g->last_rounds = rounds;
     double ms_relax = 0.0;
     for (size_t i = 0; i + 1 < nkev; i += 2) {

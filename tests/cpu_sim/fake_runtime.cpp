@@ -135,6 +135,9 @@ hipError_t launch_round(const VorParams &P, uint32_t, uint32_t, hipStream_t) {
 
 int persistent_max_grid(uint32_t) { return 0; }
 int round_max_grid(uint32_t) { return 0; }
+int cluster_max_grid() { return 0; }
+hipError_t launch_cluster_start(const ClusterParams &, const uint32_t *, uint32_t, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_cluster_round(const ClusterParams &, uint32_t, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_persistent(const VorParams &, uint32_t, uint32_t, uint32_t, hipStream_t) { return hipErrorInvalidValue; }
 
 hipError_t launch_scan(const ScanParams &S, uint32_t, uint32_t, hipStream_t) {

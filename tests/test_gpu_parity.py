@@ -26,6 +26,7 @@ OPTION_SETS = {
     "persist_odd": dict(driver=2, small_max=2, chunk=64, delta=3, block=1024),
     "bucketed": dict(delta=50),
     "lazy": dict(flags=st.FLAG_LAZY_PRED),
+    "cluster": dict(driver=3),
     "eager": dict(flags=st.FLAG_EAGER_PRED),
     "split": dict(delta=50, flags=st.FLAG_SPLIT),
     "split_chunky": dict(delta=7, flags=st.FLAG_SPLIT, small_max=1, chunk=64, local_iters=0xFFFFFFFF),
@@ -141,7 +142,7 @@ def test_upload_validation(stream):
 def test_er16k_config(stream):
     g = W.make_graph("er16k")
     seeds = W.make_seeds(g, 16)
-    for name in ("default", "host", "persistent", "delta1", "bucketed", "split", "chunky", "lazy", "eager"):
+    for name in ("default", "host", "persistent", "delta1", "bucketed", "split", "chunky", "lazy", "eager", "cluster"):
         say(f"er16k options={name}")
         check_case(g, seeds, stream, OPTION_SETS[name], f"er16k {name}")
 
@@ -151,7 +152,7 @@ def test_rmat_hubs(stream):
     cand = W.lcc(g)
     for k in (2, 37, 1000):
         seeds = W.sample(cand, k, master=3)
-        for name in ("default", "persistent", "chunky", "split", "eager"):
+        for name in ("default", "persistent", "chunky", "split", "eager", "cluster"):
             say(f"rmat16 k={k} options={name}")
             check_case(g, seeds, stream, OPTION_SETS[name], f"rmat16 k={k} {name}")
 
@@ -159,12 +160,12 @@ def test_rmat_hubs(stream):
 def test_weight_one_ties(stream):
     g = W.rmat(13, 8, wlo=1, whi=1)
     seeds = W.sample(W.lcc(g), 300, master=5)
-    for name in ("default", "persistent", "bucketed", "split_chunky", "eager", "lazy"):
+    for name in ("default", "persistent", "bucketed", "split_chunky", "eager", "lazy", "cluster"):
         say(f"rmat13 unit weights options={name}")
         check_case(g, seeds, stream, OPTION_SETS[name], f"unit {name}")
     gg = W.grid(61, 67, 1, 2)
     seeds = W.sample(np.arange(gg.n, dtype=np.uint32), 150, master=6)
-    for name in ("default", "persistent", "lazy"):
+    for name in ("default", "persistent", "lazy", "cluster"):
         say(f"grid 61x67 w in [1,2] options={name}")
         check_case(gg, seeds, stream, OPTION_SETS[name], f"grid12 {name}")
 
@@ -177,7 +178,7 @@ def test_grid2048_full_size(stream):
     assert ref.code == O.OK
     want_key = O.packed_key(ref.dist, ref.src)
     with st.Graph(g, 0, stream) as dg:
-        for name in ("default", "persistent", "lazy"):
+        for name in ("default", "persistent", "lazy", "cluster"):
             say(f"grid2048 options={name}")
             tree = dg.solve(seeds, OPTION_SETS[name])
             assert tree.edges == ref.edges and tree.total == ref.total
