@@ -22,6 +22,6 @@ def pytest_configure(config):
         workloads.build()
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build()
-    import checker
-    if checker.stale():
-        checker.build()
+    import props
+    if props.stale():
+        props.build()

@@ -1,4 +1,4 @@
-/* Test-side checker (test infrastructure, shares nothing with the library):
+/* Test-side property verifier (test infrastructure, shares nothing with the library):
  * properties that pin the unique results of Alg. 2 Steps 1 and 2 at sizes
  * where the oracle's full solve is too slow.  Keys are (dist << 32) | seed
  * index, all ones = unreached, as in the library's output. */

@@ -1,4 +1,4 @@
-"""Binding of the test-side property checker (tests/checker.c): the Voronoi
+"""Binding of the test-side property verifier (tests/props.c): the Voronoi
 fixed-point equations and the exactness of G'1, for sizes the oracle's full
 solve cannot reach in a test."""
 import ctypes
@@ -8,8 +8,8 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "checker.c")
-LIB = os.path.join(HERE, "libchecker.so")
+SRC = os.path.join(HERE, "props.c")
+LIB = os.path.join(HERE, "libprops.so")
 _lib = None
 
 

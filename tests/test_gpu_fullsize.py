@@ -9,7 +9,7 @@ import sys
 import numpy as np
 import pytest
 
-import checker
+import props
 import oracle as O
 import paper_2205_14503_amd as st
 import workloads as W
@@ -39,7 +39,7 @@ def verify_by_properties(g, seeds, dg, tree, what):
     key, pred = dg.voronoi(seeds)
     gi, gj, gk = dg.boundary(seeds)
     say(f"{what}: checking the Voronoi fixed point")
-    assert checker.voronoi_fixed_point(g, S, key) == -1
+    assert props.voronoi_fixed_point(g, S, key) == -1
     reached = key != U64_MAX
     dist = np.where(reached, key >> np.uint64(32), U64_MAX).astype(np.uint64)
     src = np.where(reached, key & np.uint64(0xFFFFFFFF), np.uint64(0xFFFFFFFF)).astype(np.uint32)
@@ -49,7 +49,7 @@ def verify_by_properties(g, seeds, dg, tree, what):
     say(f"{what}: checking G'1 exactness")
     pt = np.full(k * (k - 1) // 2, U64_MAX, dtype=np.uint64)
     pt[gj.astype(np.uint64) * (gj.astype(np.uint64) - 1) // 2 + gi] = gk
-    assert checker.boundary_exact(g, key, k, pt) == 0
+    assert props.boundary_exact(g, key, k, pt) == 0
     say(f"{what}: oracle MST and expansion on the verified G'1")
     rc, chosen = O.mst(k, gi, gj, gk >> np.uint64(32))
     assert rc == O.OK and len(chosen) == k - 1

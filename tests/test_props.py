@@ -1,8 +1,8 @@
-"""The property checker accepts the oracle's Voronoi keys and G'1 and rejects
+"""The property verifier accepts the oracle's Voronoi keys and G'1 and rejects
 small corruptions of them (CPU)."""
 import numpy as np
 
-import checker
+import props
 import oracle as O
 import workloads as W
 
@@ -14,31 +14,31 @@ def _dense(k, pi, pj, pb, pe):
     return pt
 
 
-def test_checker_accepts_oracle_and_rejects_corruptions():
+def test_verifier_accepts_oracle_and_rejects_corruptions():
     for g, k in ((W.rmat(11, 8, wlo=1, whi=50, master=3), 40), (W.grid(30, 31, 1, 4, 5), 25),
                  (W.er(2000, 6000, 1, 1, 6), 60)):
         _, S = O.canon_seeds(g.n, W.sample(W.lcc(g), k, master=2))
         dist, src = O.voronoi(g, S)
         key = O.packed_key(dist, src)
-        assert checker.voronoi_fixed_point(g, S, key) == -1
+        assert props.voronoi_fixed_point(g, S, key) == -1
         rc, pi, pj, pb, pe = O.boundary(g, dist, src, len(S))
         pt = _dense(len(S), pi, pj, pb, pe)
-        assert checker.boundary_exact(g, key, len(S), pt) == 0
+        assert props.boundary_exact(g, key, len(S), pt) == 0
         # a vertex one too far, one too near, or in the wrong cell
         reached = np.nonzero((dist != np.iinfo(np.uint64).max) & (dist > 0))[0]
         v = int(reached[len(reached) // 2])
         for delta_key in ((1 << 32), -(1 << 32), 1):
             bad = key.copy()
             bad[v] = np.uint64(int(bad[v]) + delta_key)
-            assert checker.voronoi_fixed_point(g, S, bad) != -1
+            assert props.voronoi_fixed_point(g, S, bad) != -1
         # a pair entry too large (not attained), too small (below a candidate), or an extra pair
         p0 = int(np.nonzero(pt != np.iinfo(np.uint64).max)[0][0])
         for val in (int(pt[p0]) + 1, int(pt[p0]) - 1):
             bad = pt.copy()
             bad[p0] = np.uint64(val)
-            assert checker.boundary_exact(g, key, len(S), bad) != 0
+            assert props.boundary_exact(g, key, len(S), bad) != 0
         empty = np.nonzero(pt == np.iinfo(np.uint64).max)[0]
         if len(empty):
             bad = pt.copy()
             bad[empty[0]] = np.uint64(5)
-            assert checker.boundary_exact(g, key, len(S), bad) != 0
+            assert props.boundary_exact(g, key, len(S), bad) != 0
