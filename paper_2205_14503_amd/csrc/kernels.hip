@@ -1343,6 +1343,29 @@ DEVI void rank_pair(uint32_t r, uint32_t k, uint32_t *i, uint32_t *j) {
     *j = (uint32_t)(r - row_start((uint64_t)ii, k) + (uint64_t)ii + 1);
 }
 
+// atomicMin(best + root, key) for every lane with `on`.  Late rounds send many
+// edges to few roots, so the lanes sharing the roots of the first two pending
+// lanes are combined in the wave first (one atomic per such root).
+DEVI void wave_min_to_root(unsigned long long *best, uint32_t root, unsigned long long key, bool on) {
+    uint64_t pending = __ballot(on);
+    for (int it = 0; it < 2 && pending; it++) {
+        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)pending) - 1;
+        const uint32_t r = __shfl(root, (int)leader, 64);
+        const bool mine = on && root == r;
+        const uint64_t peers = __ballot(mine);
+        unsigned long long v = mine ? key : ~0ull;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            const unsigned long long o = __shfl_xor(v, d, 64);
+            v = o < v ? o : v;
+        }
+        if (lane() == leader && v < best[r]) atomicMin(best + r, v);
+        if (mine) on = false;
+        pending &= ~peers;
+    }
+    if (on && key < best[root]) atomicMin(best + root, key);
+}
+
 __global__ void k_mst_init(MstParams M, const uint32_t *g1_idx, uint32_t m) {
     const uint32_t t0 = blockIdx.x * blockDim.x + threadIdx.x, st = gridDim.x * blockDim.x;
     for (uint32_t c = t0; c < M.k; c += st) {
@@ -1367,19 +1390,21 @@ __global__ void __launch_bounds__(256) k_mst_edges(MstParams M, uint32_t in) {
     for (uint32_t base = blockIdx.x * blockDim.x; base < m; base += st) {
         const uint32_t t = base + threadIdx.x;
         bool live = false;
-        uint32_t p = 0;
+        uint32_t p = 0, ci = 0, cj = 0;
+        unsigned long long key = 0;
         if (t < m) {
             p = M.edges[in][t];
             uint32_t i, j;
             pair_of(p, &i, &j);
-            const uint32_t ci = M.par[i], cj = M.par[j];
+            ci = M.par[i];
+            cj = M.par[j];
             if (ci != cj) {
                 live = true;
-                const unsigned long long key = ((M.pt[p] >> 32) << 32) | rank_of(i, j, M.k);
-                if (key < M.best[ci]) atomicMin(M.best + ci, key);
-                if (key < M.best[cj]) atomicMin(M.best + cj, key);
+                key = ((M.pt[p] >> 32) << 32) | rank_of(i, j, M.k);
             }
         }
+        wave_min_to_root(M.best, ci, key, live);
+        wave_min_to_root(M.best, cj, key, live);
         const uint64_t mk = __ballot(live);
         if (mk) {
             const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mk) - 1;
@@ -1466,19 +1491,21 @@ __global__ void __launch_bounds__(1024) k_mst_small(MstParams M, const uint32_t 
         for (uint32_t base = 0; base < cnt; base += blockDim.x) {
             const uint32_t t = base + threadIdx.x;
             bool live = false;
-            uint32_t p = 0;
+            uint32_t p = 0, ci = 0, cj = 0;
+            unsigned long long key = 0;
             if (t < cnt) {
                 p = src[t];
                 uint32_t i, j;
                 pair_of(p, &i, &j);
-                const uint32_t ci = M.par[i], cj = M.par[j];
+                ci = M.par[i];
+                cj = M.par[j];
                 if (ci != cj) {
                     live = true;
-                    const unsigned long long key = ((M.pt[p] >> 32) << 32) | rank_of(i, j, M.k);
-                    if (key < M.best[ci]) atomicMin(M.best + ci, key);
-                    if (key < M.best[cj]) atomicMin(M.best + cj, key);
+                    key = ((M.pt[p] >> 32) << 32) | rank_of(i, j, M.k);
                 }
             }
+            wave_min_to_root(M.best, ci, key, live);
+            wave_min_to_root(M.best, cj, key, live);
             const uint64_t mk = __ballot(live);
             if (mk) {
                 const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mk) - 1;
