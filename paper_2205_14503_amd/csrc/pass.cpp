@@ -466,7 +466,9 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         if (rc) return rc;
         const uint32_t cgrid = (uint32_t)std::max(1, cluster_max_grid());
         ClusterCtl *hc = (ClusterCtl *)(hctl + L.pass);  // pinned scratch; the frontier pass control is unused here
-        uint32_t chunk_rounds = std::min<uint32_t>(std::max<uint32_t>(g->last_rounds, 4), 64), launched = 0;
+        // the previous pass's rounds plus the deciding round and one spare, then small growing chunks
+        uint32_t chunk_rounds = std::min<uint32_t>(std::max<uint32_t>(g->last_rounds + 2, 4), 256), launched = 0;
+        uint32_t next_chunk = 4;
         for (;;) {
             kmark();
             for (uint32_t i = 0; i < chunk_rounds; i++) {
@@ -483,7 +485,8 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
             if (hc->done) break;
             if (launched >= round_cap || wall() > wall_cap_s)
                 return fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)", hc->round);
-            chunk_rounds = std::min<uint32_t>(chunk_rounds * 2, 64);
+            chunk_rounds = next_chunk;
+            next_chunk = std::min<uint32_t>(next_chunk * 2, 64);
         }
         cluster_rounds = hc->round;
         hpass->round = 0;  // the frontier pass did not run
@@ -512,8 +515,9 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
                 return fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)", hpass->round);
         }
     } else if (!clustered) {
-        // the first chunk covers as many rounds as the previous pass on this graph needed
-        uint32_t chunk_rounds = std::min<uint32_t>(std::max<uint32_t>(g->last_rounds, 4), 64), launched = 0;
+        // the previous pass's rounds plus the deciding round and one spare, then small growing chunks
+        uint32_t chunk_rounds = std::min<uint32_t>(std::max<uint32_t>(g->last_rounds + 2, 4), 256), launched = 0;
+        uint32_t next_chunk = 4;
         for (;;) {
             kmark();
             for (uint32_t i = 0; i < chunk_rounds; i++) {
@@ -530,7 +534,8 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
             if (hpass->all_done) break;
             if (launched >= round_cap || wall() > wall_cap_s)
                 return fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)", hpass->round);
-            chunk_rounds = std::min<uint32_t>(chunk_rounds * 2, 64);
+            chunk_rounds = next_chunk;
+            next_chunk = std::min<uint32_t>(next_chunk * 2, 64);
         }
     }
     const uint32_t rounds = clustered ? cluster_rounds : hpass->round;
