@@ -208,7 +208,7 @@ def test_batch_equals_single_and_oracle(stream):
     sets = [W.sample(cand, int(k), master=1, stream=200 + q) for q, k in enumerate([3, 17, 2, 64, 9, 250, 5, 1])]
     sets.append(np.array([int(cand[0])] * 3, dtype=np.uint32))  # k = 1 after dedup
     with st.Graph(g, 0, stream) as dg:
-        for name in ("default", "persistent"):
+        for name in ("default", "persistent", "cluster"):  # a batch with driver 3 runs the frontier driver
             say(f"batch options={name}")
             res = dg.solve_batch(sets, OPTION_SETS[name])
             for q, (code, tree) in enumerate(res):
