@@ -33,6 +33,9 @@ FLAG_SPLIT = 4
 FLAG_LAZY_PRED = 8
 FLAG_EAGER_PRED = 16
 MAX_SEEDS = 92682
+UPLOAD_SYMMETRY = 1
+UPLOAD_REORDER = 2
+UPLOAD_KEEP_ORDER = 4
 DRIVER_DEFAULT, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
 
 EXPORTS = [

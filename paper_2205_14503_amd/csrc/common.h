@@ -83,6 +83,17 @@ struct DevGraph {
     const uint32_t *heavy_chunk_off;
     uint32_t scan_heavy;
     uint32_t scan_chunk;
+    // Internal vertex order.  Null when the ids are the caller's; otherwise
+    // the graph was renumbered at upload and results are stated in the
+    // caller's ids and CSR offsets: perm[v] is the caller's id of internal
+    // vertex v and inv its inverse; eo[e] is the edge id of entry e, the
+    // caller's CSR offset of the edge's entry leaving its smaller caller id
+    // (NONE for self-loops), and onew[f] is, for such an offset f, the
+    // edge's entry leaving its smaller internal id.
+    const uint32_t *perm;
+    const uint32_t *inv;
+    const uint32_t *eo;
+    const uint32_t *onew;
 };
 
 struct VorParams {

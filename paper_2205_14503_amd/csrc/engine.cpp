@@ -9,6 +9,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -231,6 +232,162 @@ static __global__ void k_validate_symmetry(const uint64_t *rp, const uint32_t *c
     }
 }
 
+// Renumbers the vertices by descending degree (ties by id), so that the
+// high-degree vertices, whose keys most gathers read, share few cache lines,
+// and sorts every row by the new ids (entries to one neighbour keep their
+// order).  Builds the maps that let the kernels evaluate every tie rule on
+// the caller's ids and offsets (DevGraph::perm, inv, eo, onew), so no result
+// changes.  Each entry's eo is the caller offset of its edge's entry leaving
+// the smaller caller id; a parallel group's entries are paired with their
+// twins in (weight, offset) order on both sides.  Returns 1 without touching
+// the graph if the CSR is not symmetric (some entry has no twin).
+static int reorder_graph(steiner_graph *g) {
+    const uint32_t n = g->n;
+    const uint64_t nnz = g->nnz;
+    hipStream_t s = g->stream;
+    const std::vector<uint64_t> rp = g->h_rp;  // caller's offsets
+    std::vector<uint2> adj(nnz);
+    int rc;
+    if (nnz && (rc = hip_check(hipMemcpyAsync(adj.data(), g->d_adj, nnz * 8, hipMemcpyDeviceToHost, s), "D2H adjacency")))
+        return rc;
+    if ((rc = hip_check(hipStreamSynchronize(s), "D2H adjacency"))) return rc;
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    struct Scratch {
+        std::vector<uint64_t> row;
+        std::vector<std::pair<uint32_t, uint32_t>> mine, theirs;  // (w, offset)
+    };
+    // body(v, scratch) for every v, in blocks of 1024 claimed in order; one scratch per worker
+    auto parallel_rows = [&](auto &&body) {
+        std::atomic<uint32_t> next{0};
+        auto work = [&]() {
+            Scratch sc;
+            for (;;) {
+                const uint32_t v0 = next.fetch_add(1024);
+                if (v0 >= n) return;
+                for (uint32_t v = v0; v < std::min<uint64_t>((uint64_t)v0 + 1024, n); v++) body(v, sc);
+            }
+        };
+        std::vector<std::thread> pool;
+        for (unsigned t = 1; t < nt; t++) pool.emplace_back(work);
+        work();
+        for (std::thread &t : pool) t.join();
+    };
+    // canon[f]: caller offset of the entry of f's edge that leaves the smaller caller id (NONE for self-loops)
+    std::vector<uint32_t> canon(nnz, NONE);
+    std::atomic<bool> asym{false};
+    parallel_rows([&](uint32_t u, Scratch &sc) {
+        for (uint64_t f = rp[u]; f < rp[u + 1];) {
+            const uint32_t v = adj[f].x;
+            uint64_t f1 = f;
+            while (f1 < rp[u + 1] && adj[f1].x == v) f1++;
+            if (v > u) {
+                // the run of column u in row v (rows are sorted by column)
+                uint64_t lo = rp[v], hi = rp[v + 1];
+                while (lo < hi) {
+                    const uint64_t mid = (lo + hi) / 2;
+                    if (adj[mid].x < u) lo = mid + 1; else hi = mid;
+                }
+                uint64_t g1 = lo;
+                while (g1 < rp[v + 1] && adj[g1].x == u) g1++;
+                if (g1 - lo != f1 - f) {
+                    asym = true;
+                    return;
+                }
+                if (f1 - f == 1) {
+                    if (adj[f].y != adj[lo].y) {
+                        asym = true;
+                        return;
+                    }
+                    canon[f] = (uint32_t)f;
+                    canon[lo] = (uint32_t)f;
+                } else {
+                    std::vector<std::pair<uint32_t, uint32_t>> &mine = sc.mine, &theirs = sc.theirs;
+                    mine.clear();
+                    theirs.clear();
+                    for (uint64_t t = f; t < f1; t++) mine.emplace_back(adj[t].y, (uint32_t)t);
+                    for (uint64_t t = lo; t < g1; t++) theirs.emplace_back(adj[t].y, (uint32_t)t);
+                    std::sort(mine.begin(), mine.end());
+                    std::sort(theirs.begin(), theirs.end());
+                    for (size_t t = 0; t < mine.size(); t++) {
+                        if (mine[t].first != theirs[t].first) {
+                            asym = true;
+                            return;
+                        }
+                        canon[mine[t].second] = mine[t].second;
+                        canon[theirs[t].second] = mine[t].second;
+                    }
+                }
+            }
+            f = f1;
+        }
+    });
+    if (asym) return 1;
+    // perm: stable LSD radix sort of the vertices by ~degree, two 16-bit digits
+    std::vector<uint32_t> perm(n), tmp(n), key(n);
+    for (uint32_t v = 0; v < n; v++) {
+        perm[v] = v;
+        key[v] = ~(uint32_t)std::min<uint64_t>(rp[v + 1] - rp[v], 0xFFFFFFFFu);
+    }
+    std::vector<uint32_t> cnt(65536);
+    for (int pass = 0; pass < 2; pass++) {
+        const int shift = 16 * pass;
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (uint32_t v = 0; v < n; v++) cnt[(key[v] >> shift) & 0xFFFFu]++;
+        uint32_t sum = 0;
+        for (uint32_t &c : cnt) {
+            const uint32_t x = c;
+            c = sum;
+            sum += x;
+        }
+        for (uint32_t i = 0; i < n; i++) {
+            const uint32_t v = perm[i];
+            tmp[cnt[(key[v] >> shift) & 0xFFFFu]++] = v;
+        }
+        perm.swap(tmp);
+    }
+    std::vector<uint32_t> inv(n);
+    for (uint32_t i = 0; i < n; i++) inv[perm[i]] = i;
+    std::vector<uint64_t> nrp((size_t)n + 1, 0);
+    for (uint32_t i = 0; i < n; i++) nrp[i + 1] = nrp[i] + (rp[perm[i] + 1] - rp[perm[i]]);
+    // rows in the new order, each sorted by new column id; onew points at the entry that leaves the
+    // smaller new id, the one the boundary scan reads
+    std::vector<uint2> nadj(nnz);
+    std::vector<uint32_t> eo(nnz), onew(nnz, NONE);
+    parallel_rows([&](uint32_t i, Scratch &sc) {
+        std::vector<uint64_t> &row = sc.row;
+        const uint32_t v = perm[i];
+        const uint64_t b = rp[v], d = rp[v + 1] - b;
+        row.resize(d);
+        for (uint64_t j = 0; j < d; j++) row[j] = ((uint64_t)inv[adj[b + j].x] << 32) | j;
+        std::sort(row.begin(), row.end());
+        for (uint64_t t = 0; t < d; t++) {
+            const uint64_t f = b + (uint32_t)row[t], e = nrp[i] + t;
+            const uint32_t nu = (uint32_t)(row[t] >> 32);
+            nadj[e] = make_uint2(nu, adj[f].y);
+            eo[e] = canon[f];
+            if (i < nu) onew[canon[f]] = (uint32_t)e;
+        }
+    });
+    std::vector<uint32_t> nrp32((size_t)n + 1);
+    for (size_t i = 0; i <= n; i++) nrp32[i] = (uint32_t)nrp[i];
+    if ((rc = dev_alloc((void **)&g->d_perm, (size_t)n * 4)) || (rc = dev_alloc((void **)&g->d_inv, (size_t)n * 4)) ||
+        (rc = dev_alloc((void **)&g->d_eo, nnz * 4)) || (rc = dev_alloc((void **)&g->d_onew, nnz * 4)))
+        return rc;
+    rc = hip_check(hipMemcpyAsync(g->d_rp, nrp32.data(), ((size_t)n + 1) * 4, hipMemcpyHostToDevice, s), "H2D row_ptr");
+    if (!rc && nnz) rc = hip_check(hipMemcpyAsync(g->d_adj, nadj.data(), nnz * 8, hipMemcpyHostToDevice, s), "H2D adjacency");
+    if (!rc && nnz) rc = hip_check(hipMemcpyAsync(g->d_eo, eo.data(), nnz * 4, hipMemcpyHostToDevice, s), "H2D offsets");
+    if (!rc && nnz) rc = hip_check(hipMemcpyAsync(g->d_onew, onew.data(), nnz * 4, hipMemcpyHostToDevice, s), "H2D offsets");
+    if (!rc) rc = hip_check(hipMemcpyAsync(g->d_perm, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, s), "H2D perm");
+    if (!rc) rc = hip_check(hipMemcpyAsync(g->d_inv, inv.data(), (size_t)n * 4, hipMemcpyHostToDevice, s), "H2D perm");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "reorder upload");
+    if (rc) return rc;
+    g->h_rp.swap(nrp);
+    g->h_perm.swap(perm);
+    g->h_inv.swap(inv);
+    g->reordered = true;
+    return STEINER_OK;
+}
+
 static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t *d_col, const uint32_t *d_w,
                         uint32_t flags) {
     const uint32_t n = g->n;
@@ -253,7 +410,7 @@ static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t
     uint32_t hbad = 0;
     rc = hip_check(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s), "validate");
     if (!rc) rc = hip_check(hipStreamSynchronize(s), "validate sync");
-    if (!rc && !hbad && (flags & 1u)) {
+    if (!rc && !hbad && (flags & STEINER_UPLOAD_SYMMETRY)) {
         hipLaunchKernelGGL(k_validate_symmetry, dim3(2048), dim3(256), 0, s, d_rp64, d_col, d_w, n, (uint32_t *)bad);
         rc = hip_check(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s), "symmetry");
         if (!rc) rc = hip_check(hipStreamSynchronize(s), "symmetry sync");
@@ -278,6 +435,19 @@ static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t
     if (!rc) rc = hip_check(hipStreamSynchronize(s), "convert");
     dev_free(bad);
     if (rc) return rc;
+    // Internal order: renumber skewed graphs (maximum degree at least 32 times the mean) unless the
+    // flags say otherwise.
+    bool reorder = (flags & STEINER_UPLOAD_REORDER) != 0;
+    if (!(flags & (STEINER_UPLOAD_REORDER | STEINER_UPLOAD_KEEP_ORDER)) && nnz) {
+        uint64_t mx = 0;
+        for (uint32_t v = 0; v < n; v++) mx = std::max(mx, g->h_rp[v + 1] - g->h_rp[v]);
+        reorder = (double)mx >= 32.0 * (double)nnz / (double)n;
+    }
+    if (reorder && (rc = reorder_graph(g))) {
+        if (rc != 1) return rc;
+        // an asymmetric CSR has no twin for some entry: keep the caller's order
+        if (flags & STEINER_UPLOAD_REORDER) return fail(STEINER_EINVAL, "renumbering needs a symmetric CSR");
+    }
     // Heavy rows of the boundary scan and the default bucket width.
     const uint32_t scan_heavy = 1024, scan_chunk = 1024;
     std::vector<uint32_t> hrows, hoff;
@@ -308,6 +478,10 @@ static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t
     dg.heavy_chunk_off = g->d_heavy_off;
     dg.scan_heavy = scan_heavy;
     dg.scan_chunk = scan_chunk;
+    dg.perm = g->d_perm;
+    dg.inv = g->d_inv;
+    dg.eo = g->d_eo;
+    dg.onew = g->d_onew;
     const double avg_w = nnz ? (double)wsum / (double)nnz : 1.0;
     const double avg_deg = n ? (double)nnz / (double)n : 1.0;
     // the classic bucket width (about the mean weight over the mean degree) is one of the tuner's
@@ -341,6 +515,8 @@ extern "C" int steiner_graph_upload(uint32_t n, uint64_t nnz, const uint64_t *ro
                                     const uint32_t *w, int device, void *hip_stream, uint32_t flags,
                                     steiner_graph **out) {
     if (!row_ptr || (nnz && (!col || !w))) return fail(STEINER_EINVAL, "NULL array");
+    if ((flags & STEINER_UPLOAD_REORDER) && (flags & STEINER_UPLOAD_KEEP_ORDER))
+        return fail(STEINER_EINVAL, "STEINER_UPLOAD_REORDER and STEINER_UPLOAD_KEEP_ORDER exclude each other");
     steiner_graph *g = nullptr;
     int rc = graph_create(n, nnz, device, hip_stream, &g);
     if (rc) return rc;
@@ -370,6 +546,8 @@ extern "C" int steiner_graph_upload_device(uint32_t n, uint64_t nnz, const void 
                                            const void *d_w, int device, void *hip_stream, uint32_t flags,
                                            steiner_graph **out) {
     if (!d_row_ptr || (nnz && (!d_col || !d_w))) return fail(STEINER_EINVAL, "NULL array");
+    if ((flags & STEINER_UPLOAD_REORDER) && (flags & STEINER_UPLOAD_KEEP_ORDER))
+        return fail(STEINER_EINVAL, "STEINER_UPLOAD_REORDER and STEINER_UPLOAD_KEEP_ORDER exclude each other");
     steiner_graph *g = nullptr;
     int rc = graph_create(n, nnz, device, hip_stream, &g);
     if (rc) return rc;
@@ -394,6 +572,10 @@ extern "C" int steiner_graph_free(steiner_graph *g) {
     dev_free(g->d_adj);
     dev_free(g->d_heavy_rows);
     dev_free(g->d_heavy_off);
+    dev_free(g->d_perm);
+    dev_free(g->d_inv);
+    dev_free(g->d_eo);
+    dev_free(g->d_onew);
     delete g;
     return STEINER_OK;
 }
@@ -438,7 +620,8 @@ extern "C" const char *steiner_last_error(void) { return g_last_error.c_str(); }
 
 // ===================================================================== solves
 
-// Sorted, distinct seeds; EINVAL for k == 0 or a seed >= n.
+// Distinct seeds in ascending caller-id order (seed index = position), as
+// internal ids; EINVAL for k == 0 or a seed >= n.
 int stn::canon_seeds(const steiner_graph *g, const uint32_t *seeds, uint32_t k, std::vector<uint32_t> &S) {
     if (k == 0) return fail(STEINER_EINVAL, "k must be > 0");
     if (!seeds) return fail(STEINER_EINVAL, "seeds is NULL");
@@ -449,6 +632,8 @@ int stn::canon_seeds(const steiner_graph *g, const uint32_t *seeds, uint32_t k, 
     S.erase(std::unique(S.begin(), S.end()), S.end());
     if (S.size() > STEINER_MAX_SEEDS)
         return fail(STEINER_EINVAL, "%zu distinct seeds; at most %u", S.size(), (unsigned)STEINER_MAX_SEEDS);
+    if (g->reordered)
+        for (uint32_t &s : S) s = g->h_inv[s];
     return STEINER_OK;
 }
 

@@ -148,8 +148,15 @@ struct steiner_graph {
     uint32_t *d_heavy_rows = nullptr, *d_heavy_off = nullptr;
     uint32_t nheavy = 0;
     uint64_t max_deg = 0;
+    // Internal vertex order (steiner_graph_upload flags): when renumbered, d_perm / h_perm give the
+    // caller's id of each internal vertex and d_inv / h_inv the inverse; d_eo maps each entry that
+    // leaves its smaller caller-id endpoint to the caller's CSR offset (NONE on the twin entry) and
+    // d_onew maps those offsets back.  All null / empty when the caller's order is kept.
+    bool reordered = false;
+    uint32_t *d_perm = nullptr, *d_inv = nullptr, *d_eo = nullptr, *d_onew = nullptr;
+    std::vector<uint32_t> h_perm, h_inv;
     stn::DevGraph dg{};
-    std::vector<uint64_t> h_rp;  // host copy of the row offsets
+    std::vector<uint64_t> h_rp;  // host copy of the (internal) row offsets
     uint32_t default_delta = 0xFFFFFFFFu;
     uint32_t classic_delta = 1;
     uint32_t tuned_delta = 0;    // set by steiner_graph_tune
@@ -170,7 +177,7 @@ namespace stn {
 
 // One query of a pass.
 struct Query {
-    std::vector<uint32_t> S;   // sorted distinct seeds
+    std::vector<uint32_t> S;   // distinct seeds as internal ids, in ascending caller-id order (seed index = position)
     int status = STEINER_OK;
     std::unique_ptr<steiner_result> result;
     // debug outputs

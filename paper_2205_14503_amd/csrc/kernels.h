@@ -8,7 +8,7 @@ struct ScanParams {
     DevGraph g;
     const uint64_t *key;   // [slots * n]
     uint32_t *aux;         // [slots * n] -> pred
-    uint32_t *heavy_pe;    // [slots * nheavy] first qualifying CSR offset of each heavy row
+    uint32_t *heavy_pe;    // [slots * nheavy] smallest caller id of a qualifying neighbour of each heavy row
     uint64_t *const *pt;   // device array of per-slot pair-table pointers
     const uint32_t *slot_ids; // slots to scan
     uint32_t nscan;        // number of slots in slot_ids
@@ -33,7 +33,7 @@ struct ExpandParams {
     DevGraph g;
     const uint64_t *key;     // slot base
     uint32_t *pred;          // slot base: pred of rows above scan_heavy on entry; the walks add the others
-    const uint32_t *sel_e;   // chosen cross-cell edge ids (CSR offsets)
+    const uint32_t *sel_e;   // chosen cross-cell edge ids (caller CSR offsets, see DevGraph::onew)
     const uint32_t *nsel;    // their number (device)
     uint32_t nsel_max;       // upper bound of *nsel, sizes the launch
     uint32_t *mark;          // n bytes (rounded up to 4), all zero on entry and again on exit
@@ -78,7 +78,7 @@ struct MstParams {
     uint32_t *par;            // [k] component root of each seed
     uint32_t *hook;           // [k] parent of each root after the current round's hooking
     unsigned long long *best; // [k] lightest key leaving each root
-    uint32_t *sel;            // [k] chosen cross-cell edge ids (CSR offsets), hdr[2] of them
+    uint32_t *sel;            // [k] chosen cross-cell edge ids (caller CSR offsets), hdr[2] of them
 };
 hipError_t launch_mst(const MstParams &M, const uint32_t *g1_idx, uint32_t m, hipStream_t s);
 

@@ -829,7 +829,7 @@ __global__ void k_slot_clear(uint64_t *key, uint32_t *aux, uint8_t *dirty, uint8
         heavy_pe[h] = NONE;
 }
 
-// Seeds of one query (sorted, distinct; seed index = position) become the
+// Seeds of one query (distinct; seed index = position) become the
 // cells' roots (Alg. 3 initialisation) and the frontier of the current round.
 __global__ void k_slot_seed(VorParams P, uint32_t slot, const uint32_t *seeds, uint32_t k) {
     const uint32_t r = P.pass->round;
@@ -876,7 +876,8 @@ struct ScanWave {
     uint32_t incl[64];
     uint32_t beg[64];
     uint32_t row[64];
-    uint32_t found[64];
+    uint32_t found[64];  // 1: the row needs no pred search (seed, unreached, or pred not wanted)
+    uint32_t best[64];   // smallest caller id of a qualifying neighbour so far
     uint64_t key[64];
 };
 
@@ -884,12 +885,25 @@ DEVI uint64_t pair_index(uint32_t i, uint32_t j) {  // i < j
     return (uint64_t)j * (j - 1) / 2 + i;
 }
 
-// Cross-cell candidate of the half edge row -> u (row < u) at CSR offset e.
+// Edge id of entry e: the caller's CSR offset of the edge's entry leaving
+// its smaller caller id.  Each edge is scanned once, from its entry leaving
+// the smaller (internal) id.
+DEVI uint32_t edge_id(const DevGraph &g, uint32_t e) { return g.eo ? g.eo[e] : e; }
+
+// Caller id of internal vertex v.
+DEVI uint32_t caller_id(const DevGraph &g, uint32_t v) { return g.perm ? g.perm[v] : v; }
+// Internal vertex of caller id c.
+DEVI uint32_t internal_id(const DevGraph &g, uint32_t c) { return g.inv ? g.inv[c] : c; }
+
 DEVI void set_err(uint32_t *err, uint32_t bit) {
     if (!(*err & bit)) atomicOr(err, bit);
 }
 
-DEVI void boundary_candidate(uint64_t *pt, uint32_t *err, uint64_t krow, uint64_t ku, uint32_t w, uint32_t e) {
+// Cross-cell candidate of the edge of entry e, row -> u (row < u).  The
+// edge id is loaded only if the sum does not already lose to the pair's
+// current entry.
+DEVI void boundary_candidate(const DevGraph &g, uint64_t *pt, uint32_t *err, uint64_t krow, uint64_t ku, uint32_t w,
+                             uint32_t e) {
     const uint32_t i1 = (uint32_t)krow, i2 = (uint32_t)ku;
     if (i1 == i2) return;
     const uint64_t bsum = (krow >> 32) + (uint64_t)w + (ku >> 32);
@@ -897,17 +911,19 @@ DEVI void boundary_candidate(uint64_t *pt, uint32_t *err, uint64_t krow, uint64_
         set_err(err, ERR_SUM_OVERFLOW);
         return;
     }
-    const uint64_t val = (bsum << 32) | e;
     uint64_t *p = pt + pair_index(min(i1, i2), max(i1, i2));
-    if (val < *p) atomicMin((unsigned long long *)p, (unsigned long long)val);
+    const uint64_t cur = *p;
+    if (bsum > (cur >> 32)) return;
+    const uint64_t val = (bsum << 32) | edge_id(g, e);
+    if (val < cur) atomicMin((unsigned long long *)p, (unsigned long long)val);
 }
 
 // One wave scans the rows of group grp (64 consecutive vertices of at most
 // scan_heavy entries each), 64 entries per step.  Every edge {a, b}, a < b,
 // is a boundary candidate from row a.  With pred, every entry of a reached
-// row gathers its neighbour's key (the first qualifying entry of the row is
-// pred); without, only entries a -> b with a < b do, unreached rows included,
-// which still sees every edge once for the overflow test.
+// row gathers its neighbour's key and pred is the qualifying neighbour of
+// smallest caller id; without, only entries a -> b with a < b do, unreached
+// rows included, which still sees every edge once for the overflow test.
 DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *pred, uint64_t *pt, uint32_t *err,
                            uint32_t grp, ScanWave *L) {
     const uint32_t n = S.g.n, ln = lane();
@@ -942,6 +958,7 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
     L->beg[ln] = beg;
     L->row[ln] = row;
     L->found[ln] = found;
+    L->best[ln] = NONE;
     L->key[ln] = kv;
     wave_sync();
     for (uint32_t base = 0; base < total; base += 64) {
@@ -962,38 +979,30 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
         const uint32_t rj = L->row[j];
         uint32_t u = 0, w = 0;
         uint64_t ku = KEY_INF;
-        bool need = false;
+        bool need = false, side = false;
         if (valid) {
             const uint2 a = S.g.adj[e];
             u = a.x;
             w = a.y;
-            need = wp || rj < u;
+            side = rj < u;
+            need = wp || side;
             if (need) {
                 ku = key[u];
                 if ((ku == KEY_INF) != (kr == KEY_INF)) set_err(err, ERR_DIST_OVERFLOW);
             }
         }
-        if (wp) {
-            const bool q = valid && !L->found[j] && ku != KEY_INF && (uint32_t)ku == (uint32_t)kr &&
-                           (ku >> 32) + w == (kr >> 32);
-            const uint64_t mq = __ballot(q);
-            // lanes of row j in this step start at lane sj; the first qualifying one wins
-            const uint32_t sj = ex > base ? ex - base : 0;
-            const uint64_t earlier = mq & ((1ull << ln) - 1ull) & ~((1ull << sj) - 1ull);
-            if (q && earlier == 0) {
-                pred[rj] = u;
-                L->found[j] = 1;
-            }
-        }
-        if (need && rj < u && ku != KEY_INF && kr != KEY_INF) boundary_candidate(pt, err, kr, ku, w, e);
+        if (wp && valid && !L->found[j] && ku != KEY_INF && (uint32_t)ku == (uint32_t)kr && (ku >> 32) + w == (kr >> 32))
+            atomicMin(&L->best[j], caller_id(S.g, u));
+        if (side && ku != KEY_INF && kr != KEY_INF) boundary_candidate(S.g, pt, err, kr, ku, w, e);
         wave_sync();
     }
+    if (wp && !found) pred[row] = L->best[ln] == NONE ? NONE : internal_id(S.g, L->best[ln]);
 }
 
 // One wave scans one chunk of a row above scan_heavy: boundary candidates and
-// the row's first qualifying offset (atomicMin into heavy_pe).  An unreached
-// row only checks its edges a -> b, a < b, for the overflow test (without
-// pred; with pred every reached row checks all of its own entries).
+// the smallest caller id of a qualifying neighbour (atomicMin into heavy_pe).
+// An unreached row only checks its edges a -> b, a < b, for the overflow test
+// (without pred; with pred every reached row checks all of its own entries).
 DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *pt, uint32_t *err,
                            uint32_t *heavy_pe, uint32_t lc) {
     // heavy row h owning chunk lc: largest h with heavy_chunk_off[h] <= lc
@@ -1029,9 +1038,9 @@ DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *p
             if (ku == KEY_INF) {
                 set_err(err, ERR_DIST_OVERFLOW);
             } else {
-                if (!is_seed && best == NONE && (uint32_t)ku == (uint32_t)kv && (ku >> 32) + a.y == (kv >> 32))
-                    best = e;
-                if (row < a.x) boundary_candidate(pt, err, kv, ku, a.y, e);
+                if (!is_seed && (uint32_t)ku == (uint32_t)kv && (ku >> 32) + a.y == (kv >> 32))
+                    best = min(best, caller_id(S.g, a.x));
+                if (row < a.x) boundary_candidate(S.g, pt, err, kv, ku, a.y, e);
             }
         }
     }
@@ -1061,7 +1070,7 @@ __global__ void __launch_bounds__(256) k_scan(ScanParams S) {
     }
 }
 
-// pred of heavy rows from the smallest qualifying CSR offset.
+// pred of heavy rows from the smallest caller id of a qualifying neighbour.
 __global__ void k_scan_heavy_pred(ScanParams S) {
     const uint32_t n = S.g.n, nh = S.g.nheavy;
     const uint64_t total = (uint64_t)nh * S.nscan;
@@ -1073,8 +1082,8 @@ __global__ void k_scan_heavy_pred(ScanParams S) {
         if (kv == KEY_INF) p = NONE;
         else if ((kv >> 32) == 0) p = row;
         else {
-            const uint32_t e = S.heavy_pe[(size_t)slot * nh + h];
-            p = e == NONE ? NONE : S.g.adj[e].x;
+            const uint32_t c = S.heavy_pe[(size_t)slot * nh + h];
+            p = c == NONE ? NONE : internal_id(S.g, c);
         }
         S.aux[(size_t)slot * n + row] = p;
     }
@@ -1148,6 +1157,8 @@ DEVI void emit_edges(const ExpandParams &E, bool on, uint32_t x, uint32_t y, uin
     if (lane() == leader) pos = atomicAdd(E.ocnt, (uint32_t)__popcll(m));
     pos = __shfl(pos, leader, 64) + lanes_below(m);
     if (on && pos < E.g.n) {
+        x = caller_id(E.g, x);
+        y = caller_id(E.g, y);
         E.oa[pos] = min(x, y);
         E.ob[pos] = max(x, y);
         E.ow[pos] = w;
@@ -1174,11 +1185,26 @@ DEVI uint32_t wave_row_of(const DevGraph &g, uint32_t e) {
 
 // pred of reached non-seed vertex x (key kx): rows above scan_heavy have it
 // from the scan; smaller rows are scanned here, 64 entries per step, for the
-// first entry (smallest neighbour, then smallest offset) of the same cell on
-// a shortest path.  Wave-uniform result, NONE if there is none.
+// neighbour of smallest caller id in the same cell on a shortest path (in the
+// caller's order, rows sorted by column, the first qualifying entry).
+// Wave-uniform result, NONE if there is none.
 DEVI uint32_t wave_pred_of(const ExpandParams &E, uint32_t x, uint64_t kx) {
     const uint32_t beg = E.g.rp[x], deg = E.g.rp[x + 1] - beg;
     if (deg > E.g.scan_heavy) return E.pred[x];
+    if (E.g.perm) {
+        uint32_t best = NONE;
+        for (uint32_t c = 0; c < deg; c += 64) {
+            const uint32_t i = c + lane();
+            if (i < deg) {
+                const uint2 a = E.g.adj[beg + i];
+                const uint64_t ku = E.key[a.x];
+                if (ku != KEY_INF && (uint32_t)ku == (uint32_t)kx && (ku >> 32) + a.y == (kx >> 32))
+                    best = min(best, E.g.perm[a.x]);
+            }
+        }
+        best = wave_min(best);
+        return best == NONE ? NONE : E.g.inv[best];
+    }
     for (uint32_t c = 0; c < deg; c += 64) {
         const uint32_t i = c + lane();
         bool q = false;
@@ -1206,7 +1232,7 @@ __global__ void __launch_bounds__(256) k_expand_walk(ExpandParams E) {
     const bool live = q < *E.nsel;
     uint32_t x = 0, v = 0, w = 0;
     if (live) {
-        const uint32_t e = E.sel_e[q];
+        const uint32_t e = E.g.onew ? E.g.onew[E.sel_e[q]] : E.sel_e[q];
         const uint2 a = E.g.adj[e];
         v = a.x;
         w = a.y;
@@ -1238,7 +1264,7 @@ __global__ void __launch_bounds__(256) k_expand_walk_ready(ExpandParams E) {
     const bool live = q < *E.nsel;
     uint32_t x = 0, v = 0, w = 0;
     if (live) {
-        const uint32_t e = E.sel_e[q];
+        const uint32_t e = E.g.onew ? E.g.onew[E.sel_e[q]] : E.sel_e[q];
         const uint2 a = E.g.adj[e];
         v = a.x;
         w = a.y;
@@ -1308,8 +1334,9 @@ __global__ void __launch_bounds__(256) k_expand_emit(ExpandParams E) {
                 if (!((word >> (8 * b)) & 0xFFu) || px[b] >= n) continue;
                 const uint32_t x = 4 * t + b;
                 if (pos < n) {
-                    E.oa[pos] = min(x, px[b]);
-                    E.ob[pos] = max(x, px[b]);
+                    const uint32_t cx = caller_id(E.g, x), cp = caller_id(E.g, px[b]);
+                    E.oa[pos] = min(cx, cp);
+                    E.ob[pos] = max(cx, cp);
                     E.ow[pos] = wx[b];
                 }
                 pos++;

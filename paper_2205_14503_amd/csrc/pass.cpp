@@ -594,14 +594,29 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     const uint32_t *h_adv = (const uint32_t *)(hctl + L.advances);
     std::vector<uint32_t> slot_err(h_err, h_err + Q), out_cnt(h_cnt, h_cnt + Q), slot_adv(h_adv, h_adv + Q);
 
-    // debug: key / pred of the single slot
+    // debug: key / pred of the single slot, indexed and valued by caller ids
     for (uint32_t s = 0; s < Q; s++) {
         Query &qq = qs[act[s]];
         if (qq.want_key && !slot_err[s]) {
-            rc = hip_check(hipMemcpyAsync(qq.want_key, P.key + (size_t)s * n, (size_t)n * 8, hipMemcpyDeviceToHost, st), "D2H key");
-            if (!rc) rc = hip_check(hipMemcpyAsync(qq.want_pred, P.aux + (size_t)s * n, (size_t)n * 4, hipMemcpyDeviceToHost, st), "D2H pred");
+            std::vector<uint64_t> ik;
+            std::vector<uint32_t> ip;
+            if (g->reordered) {
+                ik.resize(n);
+                ip.resize(n);
+            }
+            uint64_t *kd = g->reordered ? ik.data() : qq.want_key;
+            uint32_t *pd = g->reordered ? ip.data() : qq.want_pred;
+            rc = hip_check(hipMemcpyAsync(kd, P.key + (size_t)s * n, (size_t)n * 8, hipMemcpyDeviceToHost, st), "D2H key");
+            if (!rc) rc = hip_check(hipMemcpyAsync(pd, P.aux + (size_t)s * n, (size_t)n * 4, hipMemcpyDeviceToHost, st), "D2H pred");
             if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H");
             if (rc) return rc;
+            if (g->reordered) {
+                for (uint32_t v = 0; v < n; v++) {
+                    const uint32_t i = g->h_inv[v], p = ip[i];
+                    qq.want_key[v] = ik[i];
+                    qq.want_pred[v] = p < n ? g->h_perm[p] : p;
+                }
+            }
         }
     }
 

@@ -5,9 +5,52 @@
 #include <thread>
 #include <vector>
 
+#include "engine.h"
 #include "steiner.h"
 
 long hipsim_live_allocs();
+
+// The renumbering's maps against the caller's CSR: perm is a permutation by
+// non-increasing degree and inv its inverse; every internal entry is a caller
+// entry under perm; its edge id is the caller offset of the edge's entry that
+// leaves the smaller caller id, with the same weight, shared by exactly the
+// two entries of that edge; onew maps the id back to the entry leaving the
+// smaller internal id.  (Simulated device memory is host memory.)
+static bool renumbering_ok(const steiner_graph *g, const std::vector<uint64_t> &rp, const std::vector<uint32_t> &col,
+                           const std::vector<uint32_t> &w) {
+    const uint32_t n = g->n;
+    const uint64_t nnz = g->nnz;
+    if (!g->reordered || g->h_perm.size() != n || g->h_inv.size() != n) return false;
+    std::vector<int> seen(n, 0);
+    for (uint32_t i = 0; i < n; i++) {
+        const uint32_t v = g->h_perm[i];
+        if (v >= n || seen[v]++ || g->h_inv[v] != i) return false;
+        if (i && rp[v + 1] - rp[v] > rp[g->h_perm[i - 1] + 1] - rp[g->h_perm[i - 1]]) return false;
+    }
+    std::vector<int> uses(nnz, 0);
+    for (uint32_t i = 0; i < n; i++) {
+        const uint32_t v = g->h_perm[i];
+        const uint64_t b = g->d_rp[i], d = g->d_rp[i + 1] - b;
+        if (d != rp[v + 1] - rp[v] || g->h_rp[i] != b) return false;
+        for (uint64_t t = 0; t < d; t++) {
+            const uint2 a = g->d_adj[b + t];
+            if (t && a.x < g->d_adj[b + t - 1].x) return false;  // rows sorted by the new ids
+            const uint32_t u = g->h_perm[a.x], f = g->d_eo[b + t];
+            if (u == v) {
+                if (f != stn::NONE) return false;
+                continue;
+            }
+            const uint32_t lo = std::min(u, v), hi = std::max(u, v);
+            if (f < rp[lo] || f >= rp[lo + 1] || col[f] != hi || w[f] != a.y) return false;
+            uses[f]++;
+            if (i < a.x && g->d_onew[f] != b + t) return false;
+        }
+    }
+    for (uint32_t v = 0; v < n; v++)
+        for (uint64_t f = rp[v]; f < rp[v + 1]; f++)
+            if (uses[f] != (col[f] > v ? 2 : 0)) return false;
+    return true;
+}
 
 #define CHECK(c)                                                            \
     do {                                                                    \
@@ -34,6 +77,60 @@ int main() {
     badw[3] = 0;
     steiner_graph *bad = nullptr;
     CHECK(steiner_graph_upload(n, col.size(), rp.data(), col.data(), badw.data(), 0, nullptr, 0, &bad) == STEINER_EINVAL);
+    CHECK(steiner_graph_upload(n, col.size(), rp.data(), col.data(), w.data(), 0, nullptr,
+                               STEINER_UPLOAD_REORDER | STEINER_UPLOAD_KEEP_ORDER, &bad) == STEINER_EINVAL);
+    {
+        // the internal renumbering (host side: radix sort, twin matching and per-row sorts on worker
+        // threads, offset maps) on a path plus a hub joined to every vertex, which the automatic rule
+        // renumbers; every 7th path edge is doubled with weights 5 then 1 on one side and 1 then 5 on
+        // the other, every 11th vertex has a self-loop
+        const uint32_t n2 = 4096;
+        std::vector<uint64_t> rp2(n2 + 1);
+        std::vector<uint32_t> col2, w2;
+        for (uint32_t v = 0; v < n2; v++) {
+            rp2[v] = col2.size();
+            if (v == 0) {
+                for (uint32_t u = 1; u < n2; u++) { col2.push_back(u); w2.push_back(3); }
+                continue;
+            }
+            col2.push_back(0);
+            w2.push_back(3);
+            if (v > 1) {
+                col2.push_back(v - 1);
+                w2.push_back(1);
+                if ((v - 1) % 7 == 0) { col2.push_back(v - 1); w2.push_back(5); }
+            }
+            if (v % 11 == 0) { col2.push_back(v); w2.push_back(2); }
+            if (v + 1 < n2) {
+                if (v % 7 == 0) { col2.push_back(v + 1); w2.push_back(5); }
+                col2.push_back(v + 1);
+                w2.push_back(1);
+            }
+        }
+        rp2[n2] = col2.size();
+        for (uint32_t fl : {0u, (uint32_t)STEINER_UPLOAD_REORDER}) {
+            steiner_graph *g2 = nullptr;
+            CHECK(steiner_graph_upload(n2, col2.size(), rp2.data(), col2.data(), w2.data(), 0, nullptr, fl | 1u, &g2) ==
+                  STEINER_OK);
+            CHECK(renumbering_ok(g2, rp2, col2, w2));
+            const uint32_t seeds2[] = {4095, 17, 900, 17};
+            steiner_result *r2 = nullptr;
+            CHECK(steiner_solve(g2, seeds2, 4, nullptr, &r2) == STEINER_OK);
+            uint64_t m2 = 0;
+            CHECK(steiner_result_edges(r2, &m2, nullptr, nullptr, nullptr) == STEINER_OK && m2 == 2);
+            steiner_result_free(r2);
+            CHECK(steiner_graph_free(g2) == STEINER_OK);
+        }
+        // an asymmetric CSR keeps the caller's order, or is refused when renumbering is forced
+        std::vector<uint32_t> w3 = w2;
+        w3[rp2[5] + 1] = 9;
+        steiner_graph *g3 = nullptr;
+        CHECK(steiner_graph_upload(n2, col2.size(), rp2.data(), col2.data(), w3.data(), 0, nullptr, 0, &g3) == STEINER_OK);
+        CHECK(!g3->reordered);
+        CHECK(steiner_graph_free(g3) == STEINER_OK);
+        CHECK(steiner_graph_upload(n2, col2.size(), rp2.data(), col2.data(), w3.data(), 0, nullptr, STEINER_UPLOAD_REORDER,
+                                   &g3) == STEINER_EINVAL);
+    }
 
     // batch through the pass driver
     std::vector<std::vector<uint32_t>> sets = {{1, 5, 9}, {7}, {2, 2, 30}, {0, 63, 10, 20, 40}};

@@ -55,10 +55,10 @@ def gpu_code(fn, *a, **kw):
         return e.code, None
 
 
-def check_case(g, seeds, stream, options, what=""):
+def check_case(g, seeds, stream, options, what="", flags=0):
     ref = O.solve(g, seeds)
     _, S = O.canon_seeds(g.n, seeds)
-    with st.Graph(g, 0, stream) as dg:
+    with st.Graph(g, 0, stream, flags) as dg:
         code, tree = gpu_code(dg.solve, seeds, options)
         assert code == ref.code, f"{what}: status {code} vs oracle {ref.code}"
         if code == st.OK:
@@ -89,6 +89,17 @@ def test_tiny_graphs_all_options(stream):
             check_case(g, seeds, stream, opt, f"case {t} {name}")
 
 
+def test_tiny_graphs_renumbered(stream):
+    """The internal degree order changes no result: ties between equal
+    distances, parallel edges and self-loops are still decided on the
+    caller's ids and CSR offsets."""
+    cases = list(pins.tiny_cases(seed=23, count=90))
+    for name in ("default", "persistent", "lazy", "eager", "cluster", "split_chunky"):
+        say(f"tiny graphs renumbered, options={name}")
+        for t, (g, seeds) in enumerate(cases):
+            check_case(g, seeds, stream, OPTION_SETS[name], f"case {t} {name} renumbered", flags=st.UPLOAD_REORDER)
+
+
 def test_error_codes_and_edge_cases(stream):
     say("error codes")
     big = 1 << 31
@@ -106,6 +117,7 @@ def test_error_codes_and_edge_cases(stream):
     for t, (g, s) in enumerate(cases):
         for name in ("default", "persistent"):
             check_case(g, np.array(s, dtype=np.uint32), stream, OPTION_SETS[name], f"edge case {t} {name}")
+        check_case(g, np.array(s, dtype=np.uint32), stream, None, f"edge case {t} renumbered", flags=st.UPLOAD_REORDER)
     g = W.from_edges(4, [(0, 1, 1), (1, 2, 1), (2, 3, 1)])
     with st.Graph(g, 0, stream) as dg:
         assert gpu_code(dg.solve, np.array([], dtype=np.uint32))[0] == st.EINVAL
@@ -137,6 +149,32 @@ def test_upload_validation(stream):
     asym = good.w.copy(); asym[0] = 9
     assert upload(good.row_ptr, good.col, asym, flags=1) == st.EINVAL
     assert upload(good.row_ptr, good.col, asym, flags=0) == st.OK
+    assert upload(good.row_ptr, good.col, good.w, flags=st.UPLOAD_REORDER | st.UPLOAD_KEEP_ORDER) == st.EINVAL
+    assert upload(good.row_ptr, good.col, good.w, flags=st.UPLOAD_REORDER | st.UPLOAD_SYMMETRY) == st.OK
+
+
+def test_device_upload_both_orders(stream):
+    """Upload from device tensors, renumbered (the skewed graph's default) and
+    in the caller's order: same trees, keys and preds as the oracle."""
+    import torch
+    g = W.rmat(13, 16, wlo=1, whi=100)
+    seeds = W.sample(W.lcc(g), 120, master=4)
+    ref = O.solve(g, seeds)
+    _, S = O.canon_seeds(g.n, seeds)
+    want_key = O.packed_key(ref.dist, ref.src)
+    rp = torch.from_numpy(g.row_ptr.astype(np.int64)).cuda()
+    col = torch.from_numpy(g.col.view(np.int32)).cuda()
+    w = torch.from_numpy(g.w.view(np.int32)).cuda()
+    for flags in (0, st.UPLOAD_KEEP_ORDER, st.UPLOAD_REORDER):
+        say(f"device upload flags={flags}")
+        h = st.steiner_graph_upload_device(g.n, rp, col, w, 0, stream, flags)
+        try:
+            tree = st.steiner_solve(h, seeds)
+            assert tree.edges == ref.edges and tree.total == ref.total
+            key, pred = st.steiner_voronoi(h, g.n, seeds)
+            assert np.array_equal(key, want_key) and np.array_equal(pred, ref.pred)
+        finally:
+            st.steiner_graph_free(h)
 
 
 def test_er16k_config(stream):
@@ -155,6 +193,9 @@ def test_rmat_hubs(stream):
         for name in ("default", "persistent", "chunky", "split", "eager", "cluster"):
             say(f"rmat16 k={k} options={name}")
             check_case(g, seeds, stream, OPTION_SETS[name], f"rmat16 k={k} {name}")
+        for name in ("default", "eager"):  # the skewed graph is renumbered by default; also in the caller's order
+            say(f"rmat16 k={k} options={name} caller order")
+            check_case(g, seeds, stream, OPTION_SETS[name], f"rmat16 k={k} {name} kept", flags=st.UPLOAD_KEEP_ORDER)
 
 
 def test_weight_one_ties(stream):
@@ -168,6 +209,11 @@ def test_weight_one_ties(stream):
     for name in ("default", "persistent", "lazy", "cluster"):
         say(f"grid 61x67 w in [1,2] options={name}")
         check_case(gg, seeds, stream, OPTION_SETS[name], f"grid12 {name}")
+    unit_seeds = W.sample(W.lcc(g), 300, master=5)
+    for name in ("default", "lazy", "eager"):
+        say(f"unit weights, other vertex order, options={name}")
+        check_case(g, unit_seeds, stream, OPTION_SETS[name], f"unit {name} kept", flags=st.UPLOAD_KEEP_ORDER)
+        check_case(gg, seeds, stream, OPTION_SETS[name], f"grid12 {name} renumbered", flags=st.UPLOAD_REORDER)
 
 
 def test_grid2048_full_size(stream):
@@ -207,9 +253,11 @@ def test_batch_equals_single_and_oracle(stream):
     cand = W.lcc(g)
     sets = [W.sample(cand, int(k), master=1, stream=200 + q) for q, k in enumerate([3, 17, 2, 64, 9, 250, 5, 1])]
     sets.append(np.array([int(cand[0])] * 3, dtype=np.uint32))  # k = 1 after dedup
-    with st.Graph(g, 0, stream) as dg:
-        for name in ("default", "persistent", "cluster"):  # a batch with driver 3 runs the frontier driver
-            say(f"batch options={name}")
+    for flags, name in ((0, "default"), (0, "persistent"), (0, "cluster"), (st.UPLOAD_KEEP_ORDER, "default")):
+        # the skewed graph is renumbered unless the upload keeps the caller's order;
+        # a batch with driver 3 runs the frontier driver
+        with st.Graph(g, 0, stream, flags) as dg:
+            say(f"batch options={name} upload flags={flags}")
             res = dg.solve_batch(sets, OPTION_SETS[name])
             for q, (code, tree) in enumerate(res):
                 ref = O.solve(g, sets[q])
