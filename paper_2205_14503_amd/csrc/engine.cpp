@@ -232,6 +232,19 @@ static __global__ void k_validate_symmetry(const uint64_t *rp, const uint32_t *c
     }
 }
 
+// Host array left uninitialised (every element is written before it is read).
+template <typename T>
+struct HostArray {
+    T *p;
+    explicit HostArray(size_t count) : p(static_cast<T *>(::operator new(std::max<size_t>(count, 1) * sizeof(T)))) {}
+    ~HostArray() { ::operator delete(p); }
+    HostArray(const HostArray &) = delete;
+    HostArray &operator=(const HostArray &) = delete;
+    T &operator[](size_t i) { return p[i]; }
+    const T &operator[](size_t i) const { return p[i]; }
+    T *data() { return p; }
+};
+
 // Renumbers the vertices by descending degree (ties by id), so that the
 // high-degree vertices, whose keys most gathers read, share few cache lines,
 // and sorts every row by the new ids (entries to one neighbour keep their
@@ -246,7 +259,7 @@ static int reorder_graph(steiner_graph *g) {
     const uint64_t nnz = g->nnz;
     hipStream_t s = g->stream;
     const std::vector<uint64_t> rp = g->h_rp;  // caller's offsets
-    std::vector<uint2> adj(nnz);
+    HostArray<uint2> adj(nnz);
     int rc;
     if (nnz && (rc = hip_check(hipMemcpyAsync(adj.data(), g->d_adj, nnz * 8, hipMemcpyDeviceToHost, s), "D2H adjacency")))
         return rc;
@@ -272,15 +285,18 @@ static int reorder_graph(steiner_graph *g) {
         work();
         for (std::thread &t : pool) t.join();
     };
-    // canon[f]: caller offset of the entry of f's edge that leaves the smaller caller id (NONE for self-loops)
-    std::vector<uint32_t> canon(nnz, NONE);
+    // canon[f]: caller offset of the entry of f's edge that leaves the smaller caller id (NONE for
+    // self-loops); each entry is written from the row of its edge's smaller endpoint
+    HostArray<uint32_t> canon(nnz);
     std::atomic<bool> asym{false};
     parallel_rows([&](uint32_t u, Scratch &sc) {
         for (uint64_t f = rp[u]; f < rp[u + 1];) {
             const uint32_t v = adj[f].x;
             uint64_t f1 = f;
             while (f1 < rp[u + 1] && adj[f1].x == v) f1++;
-            if (v > u) {
+            if (v == u) {
+                for (uint64_t t = f; t < f1; t++) canon[t] = NONE;
+            } else if (v > u) {
                 // the run of column u in row v (rows are sorted by column)
                 uint64_t lo = rp[v], hi = rp[v + 1];
                 while (lo < hi) {
@@ -351,8 +367,9 @@ static int reorder_graph(steiner_graph *g) {
     for (uint32_t i = 0; i < n; i++) nrp[i + 1] = nrp[i] + (rp[perm[i] + 1] - rp[perm[i]]);
     // rows in the new order, each sorted by new column id; onew points at the entry that leaves the
     // smaller new id, the one the boundary scan reads
-    std::vector<uint2> nadj(nnz);
-    std::vector<uint32_t> eo(nnz), onew(nnz, NONE);
+    // (onew is read only at canonical offsets, each written below)
+    HostArray<uint2> nadj(nnz);
+    HostArray<uint32_t> eo(nnz), onew(nnz);
     parallel_rows([&](uint32_t i, Scratch &sc) {
         std::vector<uint64_t> &row = sc.row;
         const uint32_t v = perm[i];
