@@ -654,6 +654,17 @@ int stn::canon_seeds(const steiner_graph *g, const uint32_t *seeds, uint32_t k, 
     return STEINER_OK;
 }
 
+void stn::seed_ranks(const steiner_graph *g, const std::vector<uint32_t> &S, std::vector<uint32_t> &rk) {
+    rk.clear();
+    if (!g->reordered) return;
+    const uint32_t k = (uint32_t)S.size();
+    rk.resize(2ull * k);
+    uint32_t *tr = rk.data(), *ts = rk.data() + k;
+    for (uint32_t i = 0; i < k; i++) ts[i] = i;
+    std::sort(ts, ts + k, [&](uint32_t a, uint32_t b) { return S[a] < S[b]; });
+    for (uint32_t r = 0; r < k; r++) tr[ts[r]] = r;
+}
+
 extern "C" int steiner_solve(steiner_graph *g, const uint32_t *seeds, uint32_t k, const steiner_options *opt,
                              steiner_result **out) {
     if (!g || !out) return fail(STEINER_EINVAL, "NULL argument");

@@ -76,7 +76,8 @@ enum StopAfter { STOP_NEVER = 0, STOP_AFTER_SCAN = 1, STOP_AFTER_COMPACT = 2 };
 // Offsets of the per-pass control region (counters, pass control, per-slot
 // arrays) for Q slots; every array starts on a 256-byte boundary.
 struct Layout {
-    size_t counters, pass, thr, thr_prev, pt_ptr, pt_len, oidx_ptr, oval_ptr, ocap, far_min, near_mark, settle_mark,
+    size_t counters, pass, thr, thr_prev, pt_ptr, pt_len, oidx_ptr, oval_ptr, ocap, tr_ptr, ts_ptr, far_min, near_mark,
+        settle_mark,
         carry, active,
         adv, done, advances, slot_err, out_cnt, slot_ids, total;
     explicit Layout(uint32_t Q) {
@@ -95,6 +96,8 @@ struct Layout {
         oidx_ptr = take(8ull * Q);
         oval_ptr = take(8ull * Q);
         ocap = take(8ull * Q);
+        tr_ptr = take(8ull * Q);
+        ts_ptr = take(8ull * Q);
         far_min = take(12ull * Q);
         near_mark = take(12ull * Q);
         settle_mark = take(12ull * Q);
@@ -195,8 +198,12 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs);
 // walks and D.  key / pred are the query's slot arrays.  The tree's edges come
 // back sorted by (a, b, w); EDISCONNECTED if the MST has fewer than k-1 edges.
 int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
-                 const uint64_t *pt, const uint32_t *g1_idx, uint32_t m, bool pred_ready, TailScratch &ts,
-                 std::unique_ptr<steiner_result> &out, double *ms_mst, double *ms_expand);
+                 const uint64_t *pt, const uint32_t *tr, const uint32_t *g1_idx, uint32_t m, bool pred_ready,
+                 TailScratch &ts, std::unique_ptr<steiner_result> &out, double *ms_mst, double *ms_expand);
+// Pair-table ranks of a query's seeds (see pair_slot): rk[i] is the rank of
+// seed index i among the seeds ordered by internal id and rk[k + r] the seed
+// index of rank r.  Empty when the graph keeps the caller's order (identity).
+void seed_ranks(const steiner_graph *g, const std::vector<uint32_t> &S, std::vector<uint32_t> &rk);
 void pair_from_index(uint64_t p, uint32_t *i, uint32_t *j);
 int canon_seeds(const steiner_graph *g, const uint32_t *seeds, uint32_t k, std::vector<uint32_t> &S);
 uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chunk);

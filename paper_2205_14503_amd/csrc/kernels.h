@@ -10,6 +10,7 @@ struct ScanParams {
     uint32_t *aux;         // [slots * n] -> pred
     uint32_t *heavy_pe;    // [slots * nheavy] smallest caller id of a qualifying neighbour of each heavy row
     uint64_t *const *pt;   // device array of per-slot pair-table pointers
+    const uint32_t *const *tr; // device array of per-slot table ranks (null: identity), see pair_slot
     const uint32_t *slot_ids; // slots to scan
     uint32_t nscan;        // number of slots in slot_ids
     uint32_t *slot_err;    // [slots] ERR_DIST_OVERFLOW / ERR_SUM_OVERFLOW per query
@@ -19,11 +20,12 @@ struct ScanParams {
 
 struct CompactParams {
     uint64_t *const *pt;        // per-slot pair tables
+    const uint32_t *const *ts;  // per-slot seed index of each table rank (null: identity)
     const uint64_t *pt_len;     // per-slot pair-table lengths
     uint32_t *const *out_idx;   // per-slot pair index output
     uint64_t *const *out_val;   // per-slot packed value output
     const uint64_t *out_cap;    // per-slot capacities
-    uint32_t *out_cnt;          // per-slot counts
+    uint32_t *out_cnt;          // per-slot counts; the output indices are in seed-index order (i < j: j(j-1)/2 + i)
     const uint32_t *slot_ids;
     uint32_t nscan;
     PassCtl *pass;
@@ -71,7 +73,8 @@ hipError_t launch_expand(const ExpandParams &E, uint32_t emit_grid, hipStream_t 
 // k(k-1)/2 does; so the tree is the one Kruskal or Prim under that order
 // returns.  Scratch for m G'1 entries and k seeds, see MstParams.
 struct MstParams {
-    const uint64_t *pt;       // the query's pair table: (d'1 << 32) | edge id, index j(j-1)/2 + i
+    const uint64_t *pt;       // the query's pair table: (d'1 << 32) | edge id at pair_slot(i, j)
+    const uint32_t *tr;       // the query's table ranks (null: identity)
     uint32_t k;
     uint32_t *edges[2];       // [m] each: ping-pong lists of pair indices that still join two components
     uint32_t *hdr;            // [4]: edge counts of the two lists, chosen-edge count, expansion output count
@@ -81,6 +84,18 @@ struct MstParams {
     uint32_t *sel;            // [k] chosen cross-cell edge ids (caller CSR offsets), hdr[2] of them
 };
 hipError_t launch_mst(const MstParams &M, const uint32_t *g1_idx, uint32_t m, hipStream_t s);
+
+// Pair-table layout.  The entry of seed pair (i, j) lives at slot
+// r(r-1)/2 + q with q < r the table ranks of i and j: a seed's rank among the
+// query's seeds by internal vertex id.  On a renumbered graph that puts the
+// pairs of the high-degree seeds, whose large cells take most candidates,
+// into the first lines of the table; in the caller's order the rank is the
+// seed index.  Values and ties do not depend on the layout.
+__host__ __device__ inline uint64_t pair_slot(const uint32_t *tr, uint32_t i, uint32_t j) {
+    const uint32_t a = tr ? tr[i] : i, b = tr ? tr[j] : j;
+    const uint64_t q = a < b ? a : b, r = a < b ? b : a;
+    return r * (r - 1) / 2 + q;
+}
 
 // Cluster-local relaxation of one query (Alg. 2 Step 1; driver 3): the
 // vertices form BFS-grown clusters of at most CLUSTER_MAX vertices; a

@@ -878,6 +878,7 @@ struct ScanWave {
     uint32_t row[64];
     uint32_t found[64];  // 1: the row needs no pred search (seed, unreached, or pred not wanted)
     uint32_t best[64];   // smallest caller id of a qualifying neighbour so far
+    uint32_t rank[64];   // pair-table rank of the row's cell
     uint64_t key[64];
 };
 
@@ -899,11 +900,11 @@ DEVI void set_err(uint32_t *err, uint32_t bit) {
     if (!(*err & bit)) atomicOr(err, bit);
 }
 
-// Cross-cell candidate of the edge of entry e, row -> u (row < u).  The
-// edge id is loaded only if the sum does not already lose to the pair's
-// current entry.
-DEVI void boundary_candidate(const DevGraph &g, uint64_t *pt, uint32_t *err, uint64_t krow, uint64_t ku, uint32_t w,
-                             uint32_t e) {
+// Cross-cell candidate of the edge of entry e, row -> u (row < u); ra is
+// the pair-table rank of the row's cell.  The edge id is loaded only if the
+// sum does not already lose to the pair's current entry.
+DEVI void boundary_candidate(const DevGraph &g, uint64_t *pt, const uint32_t *tr, uint32_t *err, uint64_t krow,
+                             uint32_t ra, uint64_t ku, uint32_t w, uint32_t e) {
     const uint32_t i1 = (uint32_t)krow, i2 = (uint32_t)ku;
     if (i1 == i2) return;
     const uint64_t bsum = (krow >> 32) + (uint64_t)w + (ku >> 32);
@@ -911,7 +912,8 @@ DEVI void boundary_candidate(const DevGraph &g, uint64_t *pt, uint32_t *err, uin
         set_err(err, ERR_SUM_OVERFLOW);
         return;
     }
-    uint64_t *p = pt + pair_index(min(i1, i2), max(i1, i2));
+    const uint64_t rb = tr ? tr[i2] : i2, lo = min((uint64_t)ra, rb), hi = max((uint64_t)ra, rb);
+    uint64_t *p = pt + hi * (hi - 1) / 2 + lo;
     const uint64_t cur = *p;
     if (bsum > (cur >> 32)) return;
     const uint64_t val = (bsum << 32) | edge_id(g, e);
@@ -924,8 +926,8 @@ DEVI void boundary_candidate(const DevGraph &g, uint64_t *pt, uint32_t *err, uin
 // row gathers its neighbour's key and pred is the qualifying neighbour of
 // smallest caller id; without, only entries a -> b with a < b do, unreached
 // rows included, which still sees every edge once for the overflow test.
-DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *pred, uint64_t *pt, uint32_t *err,
-                           uint32_t grp, ScanWave *L) {
+DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *pred, uint64_t *pt, const uint32_t *tr,
+                           uint32_t *err, uint32_t grp, ScanWave *L) {
     const uint32_t n = S.g.n, ln = lane();
     const bool wp = S.with_pred != 0;
     const uint32_t row = grp * 64 + ln;
@@ -959,6 +961,7 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
     L->row[ln] = row;
     L->found[ln] = found;
     L->best[ln] = NONE;
+    L->rank[ln] = (tr && kv != KEY_INF) ? tr[(uint32_t)kv] : (uint32_t)kv;
     L->key[ln] = kv;
     wave_sync();
     for (uint32_t base = 0; base < total; base += 64) {
@@ -976,7 +979,7 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
         const uint32_t ex = j ? L->incl[j - 1] : 0;
         const uint32_t e = L->beg[j] + (t - ex);
         const uint64_t kr = L->key[j];
-        const uint32_t rj = L->row[j];
+        const uint32_t rj = L->row[j], raj = L->rank[j];
         uint32_t u = 0, w = 0;
         uint64_t ku = KEY_INF;
         bool need = false, side = false;
@@ -993,7 +996,7 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
         }
         if (wp && valid && !L->found[j] && ku != KEY_INF && (uint32_t)ku == (uint32_t)kr && (ku >> 32) + w == (kr >> 32))
             atomicMin(&L->best[j], caller_id(S.g, u));
-        if (side && ku != KEY_INF && kr != KEY_INF) boundary_candidate(S.g, pt, err, kr, ku, w, e);
+        if (side && ku != KEY_INF && kr != KEY_INF) boundary_candidate(S.g, pt, tr, err, kr, raj, ku, w, e);
         wave_sync();
     }
     if (wp && !found) pred[row] = L->best[ln] == NONE ? NONE : internal_id(S.g, L->best[ln]);
@@ -1003,7 +1006,7 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
 // the smallest caller id of a qualifying neighbour (atomicMin into heavy_pe).
 // An unreached row only checks its edges a -> b, a < b, for the overflow test
 // (without pred; with pred every reached row checks all of its own entries).
-DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *pt, uint32_t *err,
+DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *pt, const uint32_t *tr, uint32_t *err,
                            uint32_t *heavy_pe, uint32_t lc) {
     // heavy row h owning chunk lc: largest h with heavy_chunk_off[h] <= lc
     uint32_t lo = 0, hi = S.g.nheavy;
@@ -1029,6 +1032,7 @@ DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *p
         return;
     }
     const bool is_seed = (kv >> 32) == 0;
+    const uint32_t ra = tr ? tr[(uint32_t)kv] : (uint32_t)kv;
     uint32_t best = NONE;
     for (uint32_t e0 = beg; e0 < end; e0 += 64) {
         const uint32_t e = e0 + lane();
@@ -1040,7 +1044,7 @@ DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *p
             } else {
                 if (!is_seed && (uint32_t)ku == (uint32_t)kv && (ku >> 32) + a.y == (kv >> 32))
                     best = min(best, caller_id(S.g, a.x));
-                if (row < a.x) boundary_candidate(S.g, pt, err, kv, ku, a.y, e);
+                if (row < a.x) boundary_candidate(S.g, pt, tr, err, kv, ra, ku, a.y, e);
             }
         }
     }
@@ -1062,11 +1066,12 @@ __global__ void __launch_bounds__(256) k_scan(ScanParams S) {
         const uint32_t slot = S.slot_ids[si];
         const uint64_t *key = S.key + (size_t)slot * n;
         uint64_t *pt = S.pt[slot];
+        const uint32_t *tr = S.tr ? S.tr[slot] : nullptr;
         uint32_t *err = S.slot_err + slot;
         if (lu < ngroups)
-            scan_light_group(S, key, S.aux + (size_t)slot * n, pt, err, lu, &s_wave[w]);
+            scan_light_group(S, key, S.aux + (size_t)slot * n, pt, tr, err, lu, &s_wave[w]);
         else
-            scan_heavy_chunk(S, key, pt, err, S.heavy_pe + (size_t)slot * S.g.nheavy, lu - ngroups);
+            scan_heavy_chunk(S, key, pt, tr, err, S.heavy_pe + (size_t)slot * S.g.nheavy, lu - ngroups);
     }
 }
 
@@ -1091,9 +1096,12 @@ __global__ void k_scan_heavy_pred(ScanParams S) {
 
 // --------------------------------------------------------- G'1 compaction
 
+DEVI void pair_of(uint32_t p, uint32_t *i, uint32_t *j);
+
 // G'1 extraction: the finite entries of each query's pair table, as (pair
-// index, value).  A workgroup takes tiles of 1024 entries (each lane four,
-// coalesced) and reserves its output slots with one atomic per tile.
+// index in seed-index order, value).  A workgroup takes tiles of 1024 entries
+// (each lane four, coalesced) and reserves its output slots with one atomic
+// per tile.
 __global__ void __launch_bounds__(256) k_compact(CompactParams C) {
     __shared__ uint32_t s_wave_sum[4];
     __shared__ uint32_t s_base;
@@ -1101,6 +1109,7 @@ __global__ void __launch_bounds__(256) k_compact(CompactParams C) {
     for (uint32_t si = 0; si < C.nscan; si++) {
         const uint32_t slot = C.slot_ids[si];
         const uint64_t *pt = C.pt[slot];
+        const uint32_t *ts = C.ts ? C.ts[slot] : nullptr;
         const uint64_t len = C.pt_len[slot];
         const uint64_t tiles = (len + 1023) / 1024;
         for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {  // uniform per workgroup
@@ -1128,7 +1137,14 @@ __global__ void __launch_bounds__(256) k_compact(CompactParams C) {
                 for (int j = 0; j < 4; j++) {
                     if (val[j] == KEY_INF) continue;
                     if (pos < C.out_cap[slot]) {
-                        C.out_idx[slot][pos] = (uint32_t)(tile * 1024 + (uint64_t)j * 256 + threadIdx.x);
+                        uint32_t q = (uint32_t)(tile * 1024 + (uint64_t)j * 256 + threadIdx.x);
+                        if (ts) {  // table slot -> pair index of the two seed indices
+                            uint32_t a, b;
+                            pair_of(q, &a, &b);
+                            const uint32_t x = ts[a], y = ts[b];
+                            q = (uint32_t)pair_index(min(x, y), max(x, y));
+                        }
+                        C.out_idx[slot][pos] = q;
                         C.out_val[slot][pos] = val[j];
                     } else {
                         atomicOr(&C.pass->err, ERR_LIST_OVERFLOW);
@@ -1427,7 +1443,7 @@ __global__ void __launch_bounds__(256) k_mst_edges(MstParams M, uint32_t in) {
             cj = M.par[j];
             if (ci != cj) {
                 live = true;
-                key = ((M.pt[p] >> 32) << 32) | rank_of(i, j, M.k);
+                key = ((M.pt[pair_slot(M.tr, i, j)] >> 32) << 32) | rank_of(i, j, M.k);
             }
         }
         wave_min_to_root(M.best, ci, key, live);
@@ -1460,9 +1476,8 @@ DEVI void mst_merge_body(const MstParams &M, int *s_changed) {
             const uint32_t other = ci == c ? cj : ci;
             const bool mutual = M.best[other] == b;
             if (!mutual || c < other) {
-                const uint32_t p = (uint32_t)((uint64_t)j * (j - 1) / 2 + i);
                 const uint32_t pos = atomicAdd(M.hdr + 2, 1u);
-                if (pos < k) M.sel[pos] = (uint32_t)M.pt[p];
+                if (pos < k) M.sel[pos] = (uint32_t)M.pt[pair_slot(M.tr, i, j)];
             }
             if (!mutual || c > other) h = other;
         }
@@ -1528,7 +1543,7 @@ __global__ void __launch_bounds__(1024) k_mst_small(MstParams M, const uint32_t 
                 cj = M.par[j];
                 if (ci != cj) {
                     live = true;
-                    key = ((M.pt[p] >> 32) << 32) | rank_of(i, j, M.k);
+                    key = ((M.pt[pair_slot(M.tr, i, j)] >> 32) << 32) | rank_of(i, j, M.k);
                 }
             }
             wave_min_to_root(M.best, ci, key, live);

@@ -194,8 +194,8 @@ void TailScratch::release() {
 }
 
 int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
-                 const uint64_t *pt, const uint32_t *g1_idx, uint32_t m, bool pred_ready, TailScratch &ts,
-                 std::unique_ptr<steiner_result> &out, double *ms_mst, double *ms_expand) {
+                 const uint64_t *pt, const uint32_t *tr, const uint32_t *g1_idx, uint32_t m, bool pred_ready,
+                 TailScratch &ts, std::unique_ptr<steiner_result> &out, double *ms_mst, double *ms_expand) {
     const uint32_t n = g->n;
     int rc;
     if ((rc = ts.prepare(n, k, m, st))) return rc;
@@ -203,6 +203,7 @@ int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t
     uint8_t *base = ts.mst.as<uint8_t>();
     MstParams M{};
     M.pt = pt;
+    M.tr = tr;
     M.k = k;
     M.hdr = (uint32_t *)base;
     M.par = (uint32_t *)(base + 256);
@@ -348,10 +349,13 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         (rc = ws.items_s[0].ensure(cap_s * 8)) || (rc = ws.items_s[1].ensure(cap_s * 8)) ||
         (rc = ws.items_b[0].ensure(cap_b * 8)) || (rc = ws.items_b[1].ensure(cap_b * 8)) ||
         (rc = ws.ctl.ensure(L.total)) || (rc = ws.heavy_pe.ensure((size_t)Q * g->nheavy * 4 + 4)) ||
-        (rc = ws.seeds.ensure(sd_off[Q] * 4)) || (rc = ws.pt.ensure(pt_off[Q] * 8)) ||
+        (rc = ws.seeds.ensure(sd_off[Q] * 12 + 4)) || (rc = ws.pt.ensure(pt_off[Q] * 8)) ||
         (rc = ws.cidx.ensure(oc_off[Q] * 4)) || (rc = ws.cval.ensure(oc_off[Q] * 8)) ||
-        (rc = ws.host.ensure(std::max<size_t>(L.total, sd_off[Q] * 4) + 4096)))
+        (rc = ws.host.ensure(std::max<size_t>(L.total, sd_off[Q] * 12) + 4096)))
         return rc;
+    // seeds of every slot, then their table ranks and the inverse (renumbered graphs), concatenated
+    const bool ranked = g->reordered;
+    uint32_t *d_tr = ws.seeds.as<uint32_t>() + sd_off[Q], *d_ts = d_tr + sd_off[Q];
     uint8_t *ctl = ws.ctl.as<uint8_t>();
     uint8_t *hctl = ws.host.as<uint8_t>();
 
@@ -374,8 +378,12 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         uint64_t *h_oi = (uint64_t *)(hctl + L.oidx_ptr);
         uint64_t *h_ov = (uint64_t *)(hctl + L.oval_ptr);
         uint64_t *h_oc = (uint64_t *)(hctl + L.ocap);
+        uint64_t *h_tr = (uint64_t *)(hctl + L.tr_ptr);
+        uint64_t *h_ts = (uint64_t *)(hctl + L.ts_ptr);
         uint32_t *h_ids = (uint32_t *)(hctl + L.slot_ids);
         for (uint32_t s = 0; s < Q; s++) {
+            h_tr[s] = (uint64_t)(uintptr_t)(d_tr + sd_off[s]);
+            h_ts[s] = (uint64_t)(uintptr_t)(d_ts + sd_off[s]);
             h_ptr[s] = (uint64_t)(uintptr_t)(ws.pt.as<uint64_t>() + pt_off[s]);
             h_len[s] = pt_off[s + 1] - pt_off[s];
             h_oi[s] = (uint64_t)(uintptr_t)(ws.cidx.as<uint32_t>() + oc_off[s]);
@@ -393,12 +401,21 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
             return rc;
         if ((rc = hip_check(hipStreamSynchronize(st), "tables"))) return rc;
     }
-    // Seeds of every slot, concatenated.
+    // Seeds of every slot, concatenated (then the ranks).
     {
         uint32_t *hs = ws.host.as<uint32_t>();
-        for (uint32_t s = 0; s < Q; s++)
-            memcpy(hs + sd_off[s], qs[act[s]].S.data(), qs[act[s]].S.size() * 4);
-        if ((rc = hip_check(hipMemcpyAsync(ws.seeds.ptr, hs, sd_off[Q] * 4, hipMemcpyHostToDevice, st), "H2D seeds")))
+        std::vector<uint32_t> rk;
+        for (uint32_t s = 0; s < Q; s++) {
+            const std::vector<uint32_t> &S = qs[act[s]].S;
+            memcpy(hs + sd_off[s], S.data(), S.size() * 4);
+            if (ranked) {
+                seed_ranks(g, S, rk);
+                memcpy(hs + sd_off[Q] + sd_off[s], rk.data(), S.size() * 4);
+                memcpy(hs + 2 * sd_off[Q] + sd_off[s], rk.data() + S.size(), S.size() * 4);
+            }
+        }
+        if ((rc = hip_check(hipMemcpyAsync(ws.seeds.ptr, hs, sd_off[Q] * (ranked ? 12 : 4), hipMemcpyHostToDevice, st),
+                            "H2D seeds")))
             return rc;
         if ((rc = hip_check(hipStreamSynchronize(st), "seeds"))) return rc;
     }
@@ -555,6 +572,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     SP.aux = P.aux;
     SP.heavy_pe = ws.heavy_pe.as<uint32_t>();
     SP.pt = (uint64_t *const *)(ctl + L.pt_ptr);
+    SP.tr = ranked ? (const uint32_t *const *)(ctl + L.tr_ptr) : nullptr;
     SP.slot_ids = (const uint32_t *)(ctl + L.slot_ids);
     SP.nscan = Q;
     SP.slot_err = (uint32_t *)(ctl + L.slot_err);
@@ -568,6 +586,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     // ------------------------------------------------- G'1 compaction
     CompactParams CP{};
     CP.pt = SP.pt;
+    CP.ts = ranked ? (const uint32_t *const *)(ctl + L.ts_ptr) : nullptr;
     CP.pt_len = (const uint64_t *)(ctl + L.pt_len);
     CP.out_idx = (uint32_t *const *)(ctl + L.oidx_ptr);
     CP.out_val = (uint64_t *const *)(ctl + L.oval_ptr);
@@ -645,6 +664,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
             continue;
         }
         int trc = tree_from_g1(g, st, P.key + (size_t)s * n, P.aux + (size_t)s * n, k, ws.pt.as<uint64_t>() + pt_off[s],
+                               ranked ? d_tr + sd_off[s] : nullptr,
                                ws.cidx.as<uint32_t>() + oc_off[s], m, SP.with_pred != 0, ws.tail, qq.result,
                                o.timing ? &ms_mst : nullptr, o.timing ? &ms_expand : nullptr);
         if (trc == STEINER_EDISCONNECTED) {

@@ -27,6 +27,7 @@ namespace {
 struct Request {
     uint64_t ticket = 0;
     std::vector<uint32_t> S;
+    std::vector<uint32_t> rk;  // pair-table ranks of the seeds and their inverse (empty: identity)
     int status = STEINER_OK;
     bool done = false;
     int slot = -1;
@@ -77,9 +78,12 @@ struct PoolAlloc {
 };
 
 __global__ void k_set_slot_tables(uint64_t *pt_ptr, uint64_t *pt_len, uint64_t *oidx, uint64_t *oval, uint64_t *ocap,
-                                  uint32_t *slot_err, uint32_t *out_cnt, uint32_t slot, uint64_t pt, uint64_t len,
-                                  uint64_t oi, uint64_t ov, uint64_t cap) {
+                                  uint64_t *tr_ptr, uint64_t *ts_ptr, uint32_t *slot_err, uint32_t *out_cnt,
+                                  uint32_t slot, uint64_t pt, uint64_t len, uint64_t oi, uint64_t ov, uint64_t cap,
+                                  uint64_t tr, uint64_t ts) {
     pt_ptr[slot] = pt;
+    tr_ptr[slot] = tr;
+    ts_ptr[slot] = ts;
     pt_len[slot] = len;
     oidx[slot] = oi;
     oval[slot] = ov;
@@ -124,7 +128,14 @@ struct steiner_server {
         const uint64_t P_ = (uint64_t)k * (k - 1) / 2;
         const uint64_t oc = std::min<uint64_t>(P_, half);
         return ((8 * P_ + 255) & ~255ull) + ((4 * oc + 255) & ~255ull) + ((8 * oc + 255) & ~255ull) +
-               ((4ull * k + 255) & ~255ull);
+               ((12ull * k + 255) & ~255ull);
+    }
+    // A request's pool region: pair table, G'1 indices, G'1 values, then its seeds, their table ranks and the
+    // inverse ranks (k entries each).
+    uint32_t *seeds_of(const Request *r) const {
+        const uint64_t k = r->S.size(), P_ = k * (k - 1) / 2, oc = std::min<uint64_t>(P_, half);
+        return (uint32_t *)(pool.as<uint8_t>() + r->pool_off + ((8 * P_ + 255) & ~255ull) + ((4 * oc + 255) & ~255ull) +
+                            ((8 * oc + 255) & ~255ull));
     }
 
     void run_sched();
@@ -146,15 +157,19 @@ int steiner_server::admit(Request *r, int slot) {
     uint64_t *pt = (uint64_t *)base;
     uint32_t *oi = (uint32_t *)(base + ((8 * P_ + 255) & ~255ull));
     uint64_t *ov = (uint64_t *)((uint8_t *)oi + ((4 * oc + 255) & ~255ull));
-    uint32_t *seeds = (uint32_t *)((uint8_t *)ov + ((8 * oc + 255) & ~255ull));
+    uint32_t *seeds = seeds_of(r);
     uint8_t *c = ctl.as<uint8_t>();
     int rc = hip_check(hipMemcpyAsync(seeds, r->S.data(), 4ull * k, hipMemcpyHostToDevice, s_main), "H2D seeds");
+    if (!rc && !r->rk.empty())
+        rc = hip_check(hipMemcpyAsync(seeds + k, r->rk.data(), 8ull * k, hipMemcpyHostToDevice, s_main), "H2D ranks");
     if (rc) return rc;
+    const bool ranked = !r->rk.empty();
     hipLaunchKernelGGL(k_set_slot_tables, dim3(1), dim3(1), 0, s_main, (uint64_t *)(c + L.pt_ptr),
                        (uint64_t *)(c + L.pt_len), (uint64_t *)(c + L.oidx_ptr), (uint64_t *)(c + L.oval_ptr),
-                       (uint64_t *)(c + L.ocap), (uint32_t *)(c + L.slot_err), (uint32_t *)(c + L.out_cnt),
-                       (uint32_t)slot, (uint64_t)(uintptr_t)pt, P_, (uint64_t)(uintptr_t)oi, (uint64_t)(uintptr_t)ov,
-                       oc);
+                       (uint64_t *)(c + L.ocap), (uint64_t *)(c + L.tr_ptr), (uint64_t *)(c + L.ts_ptr),
+                       (uint32_t *)(c + L.slot_err), (uint32_t *)(c + L.out_cnt), (uint32_t)slot,
+                       (uint64_t)(uintptr_t)pt, P_, (uint64_t)(uintptr_t)oi, (uint64_t)(uintptr_t)ov, oc,
+                       ranked ? (uint64_t)(uintptr_t)(seeds + k) : 0ull, ranked ? (uint64_t)(uintptr_t)(seeds + 2 * k) : 0ull);
     if ((rc = hip_check(hipGetLastError(), "slot tables"))) return rc;
     if ((rc = hip_check(launch_fill_u64(pt, P_, KEY_INF, s_main), "pair table"))) return rc;
     rc = hip_check(launch_slot_start(P, (uint32_t)slot, seeds, k, heavy_pe.as<uint32_t>() + (size_t)slot * g->nheavy,
@@ -267,12 +282,14 @@ void steiner_server::run_tail() {
         SP.aux = P.aux;
         SP.heavy_pe = heavy_pe.as<uint32_t>();
         SP.pt = (uint64_t *const *)(c + L.pt_ptr);
+        SP.tr = g->reordered ? (const uint32_t *const *)(c + L.tr_ptr) : nullptr;
         SP.slot_ids = ids + slot;
         SP.nscan = 1;
         SP.slot_err = (uint32_t *)(c + L.slot_err);
         SP.with_pred = o.lazy_pred ? 0 : 1;
         CompactParams CP{};
         CP.pt = SP.pt;
+        CP.ts = g->reordered ? (const uint32_t *const *)(c + L.ts_ptr) : nullptr;
         CP.pt_len = (const uint64_t *)(c + L.pt_len);
         CP.out_idx = (uint32_t *const *)(c + L.oidx_ptr);
         CP.out_val = (uint64_t *const *)(c + L.oval_ptr);
@@ -298,8 +315,10 @@ void steiner_server::run_tail() {
                 const uint64_t P_ = r->pt_len;
                 uint8_t *base = pool.as<uint8_t>() + r->pool_off;
                 const uint32_t *oi = (const uint32_t *)(base + ((8 * P_ + 255) & ~255ull));
+                const uint32_t *tr = r->rk.empty() ? nullptr : seeds_of(r) + k;
                 status = tree_from_g1(g, s_tail, P.key + (size_t)slot * n, P.aux + (size_t)slot * n, k,
-                                      (const uint64_t *)base, oi, cnt, SP.with_pred != 0, tail, res, nullptr, nullptr);
+                                      (const uint64_t *)base, tr, oi, cnt, SP.with_pred != 0, tail, res, nullptr,
+                                      nullptr);
                 if (!status) res->stats.pairs = cnt;
             }
         }
@@ -390,6 +409,7 @@ extern "C" int steiner_server_submit(steiner_server *s, const uint32_t *seeds, u
     if (!s || !ticket) return fail(STEINER_EINVAL, "NULL argument");
     std::unique_ptr<Request> r(new Request());
     int rc = canon_seeds(s->g, seeds, k, r->S);
+    if (!rc) seed_ranks(s->g, r->S, r->rk);
     if (rc) return rc;
     r->t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
