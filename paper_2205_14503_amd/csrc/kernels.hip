@@ -926,6 +926,8 @@ DEVI void boundary_candidate(const DevGraph &g, uint64_t *pt, const uint32_t *tr
 // row gathers its neighbour's key and pred is the qualifying neighbour of
 // smallest caller id; without, only entries a -> b with a < b do, unreached
 // rows included, which still sees every edge once for the overflow test.
+constexpr int SCAN_UNROLL = 2;
+
 DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *pred, uint64_t *pt, const uint32_t *tr,
                            uint32_t *err, uint32_t grp, ScanWave *L) {
     const uint32_t n = S.g.n, ln = lane();
@@ -964,41 +966,77 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
     L->rank[ln] = (tr && kv != KEY_INF) ? tr[(uint32_t)kv] : (uint32_t)kv;
     L->key[ln] = kv;
     wave_sync();
-    for (uint32_t base = 0; base < total; base += 64) {
-        const uint32_t t = base + ln;
-        const bool valid = t < total;
-        uint32_t j = 0;
-        if (valid) {
-            uint32_t lo = 0, hi = 63;
-            while (lo < hi) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (L->incl[mid] > t) hi = mid; else lo = mid + 1;
+    // SCAN_UNROLL independent 64-entry steps per iteration, each level's loads issued for all of them
+    // before any is used (idle lanes read entry / vertex / slot 0), so one latency chain covers them all.
+    for (uint32_t base = 0; base < total; base += 64 * SCAN_UNROLL) {
+        bool valid[SCAN_UNROLL], side[SCAN_UNROLL], need[SCAN_UNROLL];
+        uint32_t jj[SCAN_UNROLL], e[SCAN_UNROLL], u[SCAN_UNROLL], w[SCAN_UNROLL];
+        uint64_t ku[SCAN_UNROLL];
+#pragma unroll
+        for (int s = 0; s < SCAN_UNROLL; s++) {
+            const uint32_t t = base + 64 * s + ln;
+            valid[s] = t < total;
+            uint32_t j = 0;
+            if (valid[s]) {
+                uint32_t lo = 0, hi = 63;
+                while (lo < hi) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (L->incl[mid] > t) hi = mid; else lo = mid + 1;
+                }
+                j = lo;
             }
-            j = lo;
+            const uint32_t ex = j ? L->incl[j - 1] : 0;
+            jj[s] = j;
+            e[s] = valid[s] ? L->beg[j] + (t - ex) : 0u;
         }
-        const uint32_t ex = j ? L->incl[j - 1] : 0;
-        const uint32_t e = L->beg[j] + (t - ex);
-        const uint64_t kr = L->key[j];
-        const uint32_t rj = L->row[j], raj = L->rank[j];
-        uint32_t u = 0, w = 0;
-        uint64_t ku = KEY_INF;
-        bool need = false, side = false;
-        if (valid) {
-            const uint2 a = S.g.adj[e];
-            u = a.x;
-            w = a.y;
-            side = rj < u;
-            need = wp || side;
-            if (need) {
-                ku = key[u];
-                if ((ku == KEY_INF) != (kr == KEY_INF)) set_err(err, ERR_DIST_OVERFLOW);
+#pragma unroll
+        for (int s = 0; s < SCAN_UNROLL; s++) {
+            const uint2 a = S.g.adj[e[s]];
+            u[s] = a.x;
+            w[s] = a.y;
+        }
+#pragma unroll
+        for (int s = 0; s < SCAN_UNROLL; s++) {
+            side[s] = valid[s] && L->row[jj[s]] < u[s];
+            need[s] = valid[s] && (wp || side[s]);
+            ku[s] = key[need[s] ? u[s] : 0u];
+        }
+#pragma unroll
+        for (int s = 0; s < SCAN_UNROLL; s++) {
+            const uint64_t kr = L->key[jj[s]];
+            if (!need[s]) ku[s] = KEY_INF;
+            else if ((ku[s] == KEY_INF) != (kr == KEY_INF)) set_err(err, ERR_DIST_OVERFLOW);
+            if (wp && valid[s] && !L->found[jj[s]] && ku[s] != KEY_INF && (uint32_t)ku[s] == (uint32_t)kr &&
+                (ku[s] >> 32) + w[s] == (kr >> 32))
+                atomicMin(&L->best[jj[s]], caller_id(S.g, u[s]));
+        }
+        // boundary candidates: the pair slots, then the current values, then the winners' atomics
+        uint64_t *slot[SCAN_UNROLL], bsum[SCAN_UNROLL], cur[SCAN_UNROLL];
+        bool cand[SCAN_UNROLL];
+#pragma unroll
+        for (int s = 0; s < SCAN_UNROLL; s++) {
+            const uint64_t kr = L->key[jj[s]];
+            const uint32_t i1 = (uint32_t)kr, i2 = (uint32_t)ku[s];
+            cand[s] = side[s] && ku[s] != KEY_INF && kr != KEY_INF && i1 != i2;
+            bsum[s] = (kr >> 32) + (uint64_t)w[s] + (ku[s] >> 32);
+            if (cand[s] && bsum[s] >= (1ull << 32)) {
+                set_err(err, ERR_SUM_OVERFLOW);
+                cand[s] = false;
             }
+            const uint64_t ra = L->rank[jj[s]], rb = tr ? tr[cand[s] ? i2 : 0u] : i2;
+            const uint64_t lo = min(ra, rb), hi = max(ra, rb);
+            slot[s] = pt + (cand[s] ? hi * (hi - 1) / 2 + lo : 0u);
         }
-        if (wp && valid && !L->found[j] && ku != KEY_INF && (uint32_t)ku == (uint32_t)kr && (ku >> 32) + w == (kr >> 32))
-            atomicMin(&L->best[j], caller_id(S.g, u));
-        if (side && ku != KEY_INF && kr != KEY_INF) boundary_candidate(S.g, pt, tr, err, kr, raj, ku, w, e);
-        wave_sync();
+#pragma unroll
+        for (int s = 0; s < SCAN_UNROLL; s++) cur[s] = *slot[s];
+#pragma unroll
+        for (int s = 0; s < SCAN_UNROLL; s++) {
+            if (!cand[s] || bsum[s] > (cur[s] >> 32)) continue;
+            const uint64_t val = (bsum[s] << 32) | edge_id(S.g, e[s]);
+            if (val < cur[s]) atomicMin((unsigned long long *)slot[s], (unsigned long long)val);
+        }
     }
+    wave_sync();
     if (wp && !found) pred[row] = L->best[ln] == NONE ? NONE : internal_id(S.g, L->best[ln]);
 }
 
