@@ -212,6 +212,49 @@ static __global__ void k_weight_sum(const uint32_t *w, uint64_t nnz, unsigned lo
     atomicAdd(sum, s);
 }
 
+// Twin matching for the renumbering: one wave per row, a lane per entry.  An
+// entry u -> v, u < v, without a parallel entry finds its twin v -> u by
+// binary search in row v (rows are sorted by column) and both get the edge id
+// f, the entry's own offset; self-loops get NONE.  Runs of parallel entries
+// are listed as (row, first offset) for the host.  A twin that is missing,
+// repeated or of another weight sets ctr[1] bit 0, a full list bit 1.
+static __global__ void k_twins(const uint32_t *rp, const uint2 *adj, uint32_t n, uint32_t *canon, uint2 *multi,
+                               uint32_t multi_cap, uint32_t *ctr) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t uu = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; uu < n; uu += nwaves) {
+        const uint32_t u = (uint32_t)uu, b = rp[u], end = rp[u + 1];
+        for (uint32_t f = b + lane; f < end; f += 64) {
+            const uint2 a = adj[f];
+            const uint32_t v = a.x;
+            if (f > b && adj[f - 1].x == v) continue;  // inside a run: its first entry's lane handles it
+            if (v == u) {
+                for (uint32_t t = f; t < end && adj[t].x == v; t++) canon[t] = NONE;
+                continue;
+            }
+            if (v < u) continue;  // the row of the smaller endpoint handles the edge
+            if (f + 1 < end && adj[f + 1].x == v) {
+                const uint32_t pos = atomicAdd(ctr, 1u);
+                if (pos < multi_cap) multi[pos] = make_uint2(u, f);
+                else atomicOr(ctr + 1, 2u);
+                continue;
+            }
+            const uint32_t rv = rp[v + 1];
+            uint32_t lo = rp[v], hi = rv;
+            while (lo < hi) {
+                const uint32_t mid = lo + (hi - lo) / 2;
+                if (adj[mid].x < u) lo = mid + 1; else hi = mid;
+            }
+            if (lo >= rv || adj[lo].x != u || (lo + 1 < rv && adj[lo + 1].x == u) || adj[lo].y != a.y) {
+                atomicOr(ctr + 1, 1u);
+                continue;
+            }
+            canon[f] = f;
+            canon[lo] = f;
+        }
+    }
+}
+
 // Symmetry: every entry (a, b, w) has a partner (b, a, w); checked by binary
 // search for (a, w) in row b among equal columns.
 static __global__ void k_validate_symmetry(const uint64_t *rp, const uint32_t *col, const uint32_t *w, uint32_t n,
@@ -286,57 +329,87 @@ static int reorder_graph(steiner_graph *g) {
         for (std::thread &t : pool) t.join();
     };
     // canon[f]: caller offset of the entry of f's edge that leaves the smaller caller id (NONE for
-    // self-loops); each entry is written from the row of its edge's smaller endpoint
+    // self-loops).  The device pairs the runs of one entry; a run of parallel entries u -> v, u < v, is
+    // paired here with the run v -> u in (weight, offset) order.  False if the twins do not match.
     HostArray<uint32_t> canon(nnz);
+    auto match_run = [&](uint32_t u, uint64_t f, Scratch &sc) -> bool {
+        const uint32_t v = adj[f].x;
+        uint64_t f1 = f;
+        while (f1 < rp[u + 1] && adj[f1].x == v) f1++;
+        uint64_t lo = rp[v], hi = rp[v + 1];
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) / 2;
+            if (adj[mid].x < u) lo = mid + 1; else hi = mid;
+        }
+        uint64_t g1 = lo;
+        while (g1 < rp[v + 1] && adj[g1].x == u) g1++;
+        if (g1 - lo != f1 - f) return false;
+        std::vector<std::pair<uint32_t, uint32_t>> &mine = sc.mine, &theirs = sc.theirs;
+        mine.clear();
+        theirs.clear();
+        for (uint64_t t = f; t < f1; t++) mine.emplace_back(adj[t].y, (uint32_t)t);
+        for (uint64_t t = lo; t < g1; t++) theirs.emplace_back(adj[t].y, (uint32_t)t);
+        std::sort(mine.begin(), mine.end());
+        std::sort(theirs.begin(), theirs.end());
+        for (size_t t = 0; t < mine.size(); t++) {
+            if (mine[t].first != theirs[t].first) return false;
+            canon[mine[t].second] = mine[t].second;
+            canon[theirs[t].second] = mine[t].second;
+        }
+        return true;
+    };
     std::atomic<bool> asym{false};
-    parallel_rows([&](uint32_t u, Scratch &sc) {
-        for (uint64_t f = rp[u]; f < rp[u + 1];) {
-            const uint32_t v = adj[f].x;
-            uint64_t f1 = f;
-            while (f1 < rp[u + 1] && adj[f1].x == v) f1++;
-            if (v == u) {
-                for (uint64_t t = f; t < f1; t++) canon[t] = NONE;
-            } else if (v > u) {
-                // the run of column u in row v (rows are sorted by column)
-                uint64_t lo = rp[v], hi = rp[v + 1];
-                while (lo < hi) {
-                    const uint64_t mid = (lo + hi) / 2;
-                    if (adj[mid].x < u) lo = mid + 1; else hi = mid;
-                }
-                uint64_t g1 = lo;
-                while (g1 < rp[v + 1] && adj[g1].x == u) g1++;
-                if (g1 - lo != f1 - f) {
-                    asym = true;
-                    return;
-                }
-                if (f1 - f == 1) {
-                    if (adj[f].y != adj[lo].y) {
+    {
+        const uint32_t multi_cap = 1u << 20;
+        void *d_canon = nullptr, *d_multi = nullptr, *d_ctr = nullptr;
+        uint32_t hctr[2] = {0, 0};
+        rc = dev_alloc(&d_canon, nnz * 4);
+        if (!rc) rc = dev_alloc(&d_multi, (size_t)multi_cap * 8);
+        if (!rc) rc = dev_alloc(&d_ctr, 8);
+        if (!rc) rc = hip_check(hipMemsetAsync(d_ctr, 0, 8, s), "twins");
+        if (!rc) {
+            hipLaunchKernelGGL(k_twins, dim3(4096), dim3(256), 0, s, g->d_rp, g->d_adj, n, (uint32_t *)d_canon,
+                               (uint2 *)d_multi, multi_cap, (uint32_t *)d_ctr);
+            rc = hip_check(hipGetLastError(), "twins");
+        }
+        if (!rc) rc = hip_check(hipMemcpyAsync(hctr, d_ctr, 8, hipMemcpyDeviceToHost, s), "twins");
+        if (!rc && nnz) rc = hip_check(hipMemcpyAsync(canon.data(), d_canon, nnz * 4, hipMemcpyDeviceToHost, s), "twins");
+        std::vector<uint2> multi;
+        if (!rc) rc = hip_check(hipStreamSynchronize(s), "twins");
+        if (!rc && !(hctr[1] & 3u) && hctr[0]) {
+            multi.resize(hctr[0]);
+            rc = hip_check(hipMemcpyAsync(multi.data(), d_multi, (size_t)hctr[0] * 8, hipMemcpyDeviceToHost, s), "twins");
+            if (!rc) rc = hip_check(hipStreamSynchronize(s), "twins");
+        }
+        dev_free(d_canon);
+        dev_free(d_multi);
+        dev_free(d_ctr);
+        if (rc) return rc;
+        if (hctr[1] & 1u) return 1;
+        if (hctr[1] & 2u) {  // more parallel runs than the list holds: pair every run here
+            parallel_rows([&](uint32_t u, Scratch &sc) {
+                for (uint64_t f = rp[u]; f < rp[u + 1];) {
+                    const uint32_t v = adj[f].x;
+                    uint64_t f1 = f;
+                    while (f1 < rp[u + 1] && adj[f1].x == v) f1++;
+                    if (v == u) {
+                        for (uint64_t t = f; t < f1; t++) canon[t] = NONE;
+                    } else if (v > u && !match_run(u, f, sc)) {
                         asym = true;
                         return;
                     }
-                    canon[f] = (uint32_t)f;
-                    canon[lo] = (uint32_t)f;
-                } else {
-                    std::vector<std::pair<uint32_t, uint32_t>> &mine = sc.mine, &theirs = sc.theirs;
-                    mine.clear();
-                    theirs.clear();
-                    for (uint64_t t = f; t < f1; t++) mine.emplace_back(adj[t].y, (uint32_t)t);
-                    for (uint64_t t = lo; t < g1; t++) theirs.emplace_back(adj[t].y, (uint32_t)t);
-                    std::sort(mine.begin(), mine.end());
-                    std::sort(theirs.begin(), theirs.end());
-                    for (size_t t = 0; t < mine.size(); t++) {
-                        if (mine[t].first != theirs[t].first) {
-                            asym = true;
-                            return;
-                        }
-                        canon[mine[t].second] = mine[t].second;
-                        canon[theirs[t].second] = mine[t].second;
-                    }
+                    f = f1;
                 }
-            }
-            f = f1;
+            });
+        } else {
+            Scratch sc;
+            for (const uint2 &m : multi)
+                if (!match_run(m.x, m.y, sc)) {
+                    asym = true;
+                    break;
+                }
         }
-    });
+    }
     if (asym) return 1;
     // perm: stable LSD radix sort of the vertices by ~degree, two 16-bit digits
     std::vector<uint32_t> perm(n), tmp(n), key(n);
