@@ -151,6 +151,10 @@ def test_upload_validation(stream):
     assert upload(good.row_ptr, good.col, asym, flags=0) == st.OK
     assert upload(good.row_ptr, good.col, good.w, flags=st.UPLOAD_REORDER | st.UPLOAD_KEEP_ORDER) == st.EINVAL
     assert upload(good.row_ptr, good.col, good.w, flags=st.UPLOAD_REORDER | st.UPLOAD_SYMMETRY) == st.OK
+    # renumbering needs every entry's twin: an asymmetric CSR is refused when it is forced
+    assert upload(good.row_ptr, good.col, asym, flags=st.UPLOAD_REORDER) == st.EINVAL
+    par = W.from_edges(3, [(0, 1, 4), (0, 1, 2), (1, 2, 2)])  # parallel entries of different weights
+    assert upload(par.row_ptr, par.col, par.w, flags=st.UPLOAD_REORDER | st.UPLOAD_SYMMETRY) == st.OK
 
 
 def test_device_upload_both_orders(stream):
