@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <queue>
 #include <string>
 #include <thread>
@@ -361,11 +362,15 @@ static int reorder_graph(steiner_graph *g) {
     std::atomic<bool> asym{false};
     {
         const uint32_t multi_cap = 1u << 20;
-        void *d_canon = nullptr, *d_multi = nullptr, *d_ctr = nullptr;
+        struct DevTemp {  // freed on every exit, allocation failures included
+            void *p = nullptr;
+            ~DevTemp() { dev_free(p); }
+        } t_canon, t_multi, t_ctr;
         uint32_t hctr[2] = {0, 0};
-        rc = dev_alloc(&d_canon, nnz * 4);
-        if (!rc) rc = dev_alloc(&d_multi, (size_t)multi_cap * 8);
-        if (!rc) rc = dev_alloc(&d_ctr, 8);
+        rc = dev_alloc(&t_canon.p, nnz * 4);
+        if (!rc) rc = dev_alloc(&t_multi.p, (size_t)multi_cap * 8);
+        if (!rc) rc = dev_alloc(&t_ctr.p, 8);
+        void *d_canon = t_canon.p, *d_multi = t_multi.p, *d_ctr = t_ctr.p;
         if (!rc) rc = hip_check(hipMemsetAsync(d_ctr, 0, 8, s), "twins");
         if (!rc) {
             hipLaunchKernelGGL(k_twins, dim3(4096), dim3(256), 0, s, g->d_rp, g->d_adj, n, (uint32_t *)d_canon,
@@ -381,9 +386,6 @@ static int reorder_graph(steiner_graph *g) {
             rc = hip_check(hipMemcpyAsync(multi.data(), d_multi, (size_t)hctr[0] * 8, hipMemcpyDeviceToHost, s), "twins");
             if (!rc) rc = hip_check(hipStreamSynchronize(s), "twins");
         }
-        dev_free(d_canon);
-        dev_free(d_multi);
-        dev_free(d_ctr);
         if (rc) return rc;
         if (hctr[1] & 1u) return 1;
         if (hctr[1] & 2u) {  // more parallel runs than the list holds: pair every run here
@@ -533,7 +535,14 @@ static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t
         for (uint32_t v = 0; v < n; v++) mx = std::max(mx, g->h_rp[v + 1] - g->h_rp[v]);
         reorder = (double)mx >= 32.0 * (double)nnz / (double)n;
     }
-    if (reorder && (rc = reorder_graph(g))) {
+    if (reorder) {
+        try {
+            rc = reorder_graph(g);
+        } catch (const std::bad_alloc &) {
+            rc = fail(STEINER_ENOMEM, "host memory for the renumbering is exhausted");
+        }
+    }
+    if (reorder && rc) {
         if (rc != 1) return rc;
         // an asymmetric CSR has no twin for some entry: keep the caller's order
         if (flags & STEINER_UPLOAD_REORDER) return fail(STEINER_EINVAL, "renumbering needs a symmetric CSR");
