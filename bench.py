@@ -73,8 +73,9 @@ def _pmc_per_kernel(path: str):
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
-def _config_key(delta, local, split=False) -> str:
-    return f"delta={int(delta)},local_iters={int(local)},split={int(bool(split))}"
+def _config_key(delta, local, split=False, grid=0) -> str:
+    key = f"delta={int(delta)},local_iters={int(local)},split={int(bool(split))}"
+    return key + (f",grid={int(grid)}" if grid else "")
 
 
 def pmc_summary(args):
@@ -100,7 +101,7 @@ def pmc_summary(args):
             lines.append(f"| {name} | {cnt} | {fv:.1f} | {wv:.1f} | {mb:.3f} |")
     entry["bytes_per_launch"] = entry["per_kernel"]["k_round"]["bytes"]
     data = json.load(open(TRAFFIC_FILE)) if os.path.exists(TRAFFIC_FILE) else {}
-    data.setdefault(args.workload, {})[_config_key(args.delta, args.local)] = entry
+    data.setdefault(args.workload, {})[_config_key(args.delta, args.local, False, args.grid)] = entry
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
     print(f"Copy calibration: a 1 GiB device copy reads {copy_kib / f_scale:.1f} KiB of FETCH_SIZE "
@@ -310,6 +311,7 @@ def main():
     ap.add_argument("--slots", type=int, default=32, help="serving: resident query slots")
     ap.add_argument("--budget-gb", type=int, default=96, help="serving: device memory budget")
     ap.add_argument("--local", type=int, default=0, help="local-queue depth (with --delta: skips the tuner)")
+    ap.add_argument("--grid", type=int, default=0, help="relaxation workgroups (with --delta: skips the tuner)")
     ap.add_argument("--seeds", default="uniform", help="seed strategy: uniform, bfs_level, eccentric, proximate")
     ap.add_argument("--sweep", action="store_true", help="run the sensitivity studies instead of the benchmark")
     ap.add_argument("--sweep-scale", type=int, default=22, help="RMAT scale of the sensitivity studies")
@@ -369,12 +371,14 @@ def main():
         opts["delta"] = args.delta
     if args.local:
         opts["local_iters"] = args.local
+    if args.grid:
+        opts["grid"] = args.grid
     dg = st.Graph(g, 0, stream)
     tuned = None
     if not args.no_tune and not args.delta:
         t0 = time.time()
         tuned = dg.tune(seeds)  # set-up, like the upload: picks delta and the local-queue depth
-        tuned = {"delta": tuned["delta"], "local_iters": tuned["local_iters"],
+        tuned = {"delta": tuned["delta"], "local_iters": tuned["local_iters"], "grid": tuned["grid"],
                  "split": bool(tuned["flags"] & st.FLAG_SPLIT), "lazy_pred": bool(tuned["flags"] & st.FLAG_LAZY_PRED),
                  "seconds": round(time.time() - t0, 2)}
         print(f"[bench] tuned {tuned}", file=sys.stderr, flush=True)
@@ -415,7 +419,8 @@ def main():
             delta = opts.get("delta", tuned and tuned["delta"])
             local = opts.get("local_iters", tuned and tuned["local_iters"])
             split = bool(tuned and tuned["split"])
-            ent = json.load(open(TRAFFIC_FILE)).get(args.workload, {}).get(_config_key(delta, local, split))
+            grid = opts.get("grid", tuned["grid"] if tuned else 0)
+            ent = json.load(open(TRAFFIC_FILE)).get(args.workload, {}).get(_config_key(delta, local, split, grid))
             if ent and ent.get("kernel_sha") == kernel_sha():
                 traffic = ent["bytes_per_launch"]
         except Exception:

@@ -154,7 +154,10 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
     while ((g->max_deg + r.chunk - 1) / r.chunk >= (1ull << CHUNK_BITS)) r.chunk *= 2;  // chunk index field
     // host-stepped: as many workgroups as are resident at once (the round kernel's occupancy);
     // persistent: two per CU at most, the co-residency its grid barrier needs
-    if (r.grid == 0) {
+    // one-query passes of the host-stepped driver use the tuned count, a latency-bound pass often runs
+    // faster on fewer workgroups; batches and the server keep every resident one
+    const bool given = r.grid != 0;
+    if (!given) {
         if (r.driver == 2) {
             r.grid = (uint32_t)std::max(1, g->cu_count) * 2u * (1024u / r.block);
         } else {
@@ -162,6 +165,8 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
             r.grid = resident > 0 ? (uint32_t)resident : (uint32_t)std::max(1, g->cu_count) * 4u;
         }
     }
+    r.grid_one = r.grid;
+    if (!given && r.driver != 2 && g->tuned_grid && g->tuned_grid <= r.grid && r.block == 256) r.grid_one = g->tuned_grid;
     return r;
 }
 
@@ -800,12 +805,14 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
     deltas.erase(std::unique(deltas.begin(), deltas.end()), deltas.end());
     // coarse to fine: the bucket width at the default queue depth, then the depth, then the split
     const bool lazy_default = resolve_options(g, nullptr).lazy_pred;
-    auto measure = [&](uint32_t d, uint32_t l, uint32_t split, double *t_out, bool lazy) -> int {
+    g->tuned_grid = 0;
+    auto measure = [&](uint32_t d, uint32_t l, uint32_t split, double *t_out, bool lazy, uint32_t grid = 0) -> int {
         Options o = resolve_options(g, nullptr);
         o.delta = d;
         o.local_iters = l;
         o.split = split != 0 && d != 0xFFFFFFFFu;
         o.lazy_pred = lazy;
+        if (grid) o.grid = o.grid_one = grid;
         double t_min = 1e300;
         for (int rep = 0; rep < 2; rep++) {
             std::vector<Query> qs(1);
@@ -838,6 +845,19 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
     bool best_lazy = lazy_default;
     if ((rc = measure(best_d, best_l, best_split, &t, !lazy_default))) return rc;
     if (t < best) { best = t; best_lazy = !lazy_default; }
+    // then fewer relaxation workgroups (half and three quarters of the resident count), at the chosen depth and at 8
+    uint32_t best_grid = 0;
+    const int resident = round_max_grid(256);
+    if (resident >= 8) {
+        std::vector<uint32_t> ls = {best_l};
+        if (best_l != 8) ls.push_back(8);
+        for (uint32_t l : ls)
+            for (uint32_t gsz : {(uint32_t)resident / 2, (uint32_t)resident * 3 / 4}) {
+                if ((rc = measure(best_d, l, best_split, &t, best_lazy, gsz))) return rc;
+                if (t < best) { best = t; best_l = l; best_grid = gsz; }
+            }
+    }
+    g->tuned_grid = best_grid;
     g->tuned_delta = best_d;
     g->tuned_local = best_l;
     g->tuned_split = best_split;
@@ -846,6 +866,7 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
         memset(out, 0, sizeof(*out));
         out->delta = best_d;
         out->local_iters = best_l;
+        out->grid = best_grid;
         out->flags = (best_split ? STEINER_FLAG_SPLIT : 0u) | (best_lazy ? STEINER_FLAG_LAZY_PRED : STEINER_FLAG_EAGER_PRED);
     }
     return STEINER_OK;
