@@ -59,13 +59,17 @@ struct Counters {
     uint32_t bar_count;  // persistent-kernel grid barrier
     uint32_t bar_gen;
     uint32_t abort;      // set when a barrier wait gives up
-    uint32_t blocks_done; // workgroups finished in the current round (last one decides)
+    uint32_t blocks_done; // workgroup groups finished in the current round (the last one decides)
     uint32_t pad[6];
+    // workgroups finished per group (blockIdx mod ROUND_GROUPS), one counter per 128-byte line: the round's
+    // completion count takes ROUND_GROUPS short chains of device-scope atomics instead of one long one
+    uint32_t grp_done[8 * 32];
     // event counters (only with counting enabled): relaxation attempts,
     // atomicMins issued, improvements, local-queue pushes, next-round pushes,
     // parked vertices, items expanded
     unsigned long long ev[8];
 };
+constexpr uint32_t ROUND_GROUPS = 8;
 enum { EV_ATTEMPT = 0, EV_ATOMIC, EV_IMPROVED, EV_LOCAL, EV_GLOBAL, EV_PARK, EV_ITEMS, EV_N };
 
 struct DevGraph {

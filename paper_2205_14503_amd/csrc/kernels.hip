@@ -632,9 +632,17 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
     relax_round_body(P, R, P.slot.thr, cs, cb, &s_wave[w], wave_gid, nwaves);
 
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {  // the last workgroup of its group, then the last group, takes the decision
         __threadfence();
-        s_last = atomicAdd(&P.cnt->blocks_done, 1u) == gridDim.x - 1;
+        const uint32_t ng = min(gridDim.x, ROUND_GROUPS), grp = blockIdx.x % ng;
+        const uint32_t gsize = (gridDim.x - grp + ng - 1) / ng;  // workgroups with this residue
+        uint32_t *gc = P.cnt->grp_done + grp * 32;
+        s_last = 0;
+        if (atomicAdd(gc, 1u) == gsize - 1) {
+            *gc = 0;  // every workgroup of the group has counted: ready for the next round
+            __threadfence();
+            s_last = atomicAdd(&P.cnt->blocks_done, 1u) == ng - 1;
+        }
     }
     __syncthreads();
     if (!s_last) return;
@@ -800,6 +808,7 @@ __global__ void k_pass_reset(VorParams P) {
         P.cnt->blocks_done = 0;
         for (int i = 0; i < EV_N; i++) P.cnt->ev[i] = 0;
     }
+    for (uint32_t i = t; i < ROUND_GROUPS * 32; i += gridDim.x * blockDim.x) P.cnt->grp_done[i] = 0;
     for (uint32_t q = t; q < P.nslots; q += gridDim.x * blockDim.x) {
         for (int b = 0; b < 3; b++) {
             P.far_min[(size_t)b * P.nslots + q] = DIST_INF;
