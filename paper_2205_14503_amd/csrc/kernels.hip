@@ -374,10 +374,11 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
 
 // The 64 smallest-distance entries of the local queue's cnt > 64 entries at
 // ring positions [h, h + cnt) are returned in the lanes' registers; the others
-// move to [h + 64, h + cnt).  Bitonic: each half is sorted across the wave
-// (the second half in reverse), then one min/max step splits them.  The sort
-// key is the distance, clamped, with the ring position as payload; order only
-// steers the work, never the result.
+// move to [h + 64, h + cnt).  The sort key is the distance, clamped, with the
+// ring position below it, so the keys are distinct: a radix search over the
+// key bits (two ballots per bit) finds the 64th smallest, and ballot prefixes
+// place the selected entries (one per lane, through LDS) and the rest.  Order
+// only steers the work, never the result.
 DEVI void lq_select(WaveScratch *L, uint32_t h, uint32_t cnt, uint64_t &item, uint64_t &kv, uint32_t &beg,
                     uint32_t &deg) {
     const uint32_t ln = lane();
@@ -392,43 +393,48 @@ DEVI void lq_select(WaveScratch *L, uint32_t h, uint32_t cnt, uint64_t &item, ui
             a[j] = (min(d, (1u << 25) - 2) << 7) | pos;
         }
     }
+    uint32_t x = 0;  // the largest value with at most 63 keys below it: the 64th smallest key
 #pragma unroll
-    for (uint32_t k = 2; k <= 64; k <<= 1) {
+    for (int bit = 31; bit >= 0; bit--) {
+        const uint32_t y = x | (1u << bit);
+        const uint32_t below = (uint32_t)__popcll(__ballot(a[0] < y)) + (uint32_t)__popcll(__ballot(a[1] < y));
+        x = below <= 63 ? y : x;
+    }
+    const bool s0 = a[0] <= x, s1 = a[1] <= x;
+    const bool q0 = !s0 && a[0] != 0xFFFFFFFFu, q1 = !s1 && a[1] != 0xFFFFFFFFu;
+    const uint64_t m0 = __ballot(s0), m1 = __ballot(s1), n0 = __ballot(q0), n1 = __ballot(q1);
+    uint32_t *slot = L->incl;  // free until the expansion rebuilds it
+    if (s0) slot[lanes_below(m0)] = a[0] & (LQ_CAP - 1);
+    if (s1) slot[(uint32_t)__popcll(m0) + lanes_below(m1)] = a[1] & (LQ_CAP - 1);
+    // the rest: every entry is read before any is written
+    uint64_t r_item[2] = {0, 0}, r_key[2] = {0, 0};
+    uint32_t r_beg[2] = {0, 0}, r_deg[2] = {0, 0};
 #pragma unroll
-        for (uint32_t d = k >> 1; d > 0; d >>= 1) {
-            const bool lower = (ln & d) == 0;
-#pragma unroll
-            for (int j = 0; j < 2; j++) {
-                const uint32_t p = (uint32_t)__shfl_xor((int)a[j], (int)d, 64);
-                const bool asc = ((ln & k) == 0) != (j == 1);
-                a[j] = (lower == asc) ? min(a[j], p) : max(a[j], p);
-            }
+    for (int j = 0; j < 2; j++) {
+        if (j ? q1 : q0) {
+            const uint32_t p = a[j] & (LQ_CAP - 1);
+            r_item[j] = L->lq_item[p];
+            r_key[j] = L->lq_key[p];
+            r_beg[j] = L->lq_beg[p];
+            r_deg[j] = L->lq_deg[p];
         }
     }
-    const uint32_t lo = min(a[0], a[1]), hi = max(a[0], a[1]);
-    const uint32_t pb = lo & (LQ_CAP - 1);
+    wave_sync();
+    const uint32_t pb = slot[ln];
     item = L->lq_item[pb];
     kv = L->lq_key[pb];
     beg = L->lq_beg[pb];
     deg = L->lq_deg[pb];
-    const bool rest = hi != 0xFFFFFFFFu;
-    const uint32_t pr = hi & (LQ_CAP - 1);
-    uint64_t r_item = 0, r_key = 0;
-    uint32_t r_beg = 0, r_deg = 0;
-    if (rest) {
-        r_item = L->lq_item[pr];
-        r_key = L->lq_key[pr];
-        r_beg = L->lq_beg[pr];
-        r_deg = L->lq_deg[pr];
-    }
-    const uint64_t m = __ballot(rest);
     wave_sync();
-    if (rest) {
-        const uint32_t at = (h + 64 + lanes_below(m)) % LQ_CAP;
-        L->lq_item[at] = r_item;
-        L->lq_key[at] = r_key;
-        L->lq_beg[at] = r_beg;
-        L->lq_deg[at] = r_deg;
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        if (j ? q1 : q0) {
+            const uint32_t at = (h + 64 + (j ? (uint32_t)__popcll(n0) + lanes_below(n1) : lanes_below(n0))) % LQ_CAP;
+            L->lq_item[at] = r_item[j];
+            L->lq_key[at] = r_key[j];
+            L->lq_beg[at] = r_beg[j];
+            L->lq_deg[at] = r_deg[j];
+        }
     }
     wave_sync();
 }
