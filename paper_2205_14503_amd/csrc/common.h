@@ -75,6 +75,7 @@ enum { EV_ATTEMPT = 0, EV_ATOMIC, EV_IMPROVED, EV_LOCAL, EV_GLOBAL, EV_PARK, EV_
 struct DevGraph {
     uint32_t n;
     uint32_t nnz;
+    uint32_t max_deg;     // largest row (clamped to 2^32 - 1)
     const uint32_t *rp;   // row offsets, n+1 (32-bit: nnz < 2^32)
     const uint2 *adj;     // (col, w) per CSR entry
     // Rows of degree > scan_heavy are split into chunks of scan_chunk edges

@@ -574,6 +574,7 @@ static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t
     DevGraph &dg = g->dg;
     dg.n = n;
     dg.nnz = (uint32_t)nnz;
+    dg.max_deg = (uint32_t)std::min<uint64_t>(g->max_deg, 0xFFFFFFFFull);
     dg.rp = g->d_rp;
     dg.adj = g->d_adj;
     dg.nheavy = g->nheavy;

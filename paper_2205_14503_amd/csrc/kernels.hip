@@ -120,7 +120,7 @@ DEVI void append_b(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, 
 // hop).  Anything the queue cannot hold goes to the next round's list.
 constexpr uint32_t LQ_CAP = 128;
 constexpr uint32_t OUT_CAP = 128;
-static_assert(LQ_CAP == 128, "lq_select packs a 7-bit ring position");
+static_assert(LQ_CAP == 128, "lq_select holds two queue entries per lane");
 
 struct WaveScratch {
     uint32_t incl[64];
@@ -279,7 +279,9 @@ DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr
 // Expands one frontier item per lane: the row [beg, beg + deg) of a vertex
 // with key kv in query `slot` (deg = 0 for idle lanes), 64 * UNROLL edges per
 // step, balanced across the wave by a prefix sum of the degrees (coalesced
-// 8-byte (col, w) loads within each row).
+// 8-byte (col, w) loads within each row).  NARROW: no row has more than
+// UNROLL entries.
+template <bool NARROW>
 DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t slot, uint32_t v,
                        uint64_t kv, uint32_t beg, uint32_t deg, bool heavy, WaveScratch *L, bool use_lq,
                        uint32_t &lq_head, uint32_t &lq_tail) {
@@ -289,6 +291,26 @@ DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *th
         P.settled[(size_t)slot * P.g.n + v] = 1;
         uint32_t *sm = P.settle_mark + (size_t)R.b * P.nslots + slot;
         if (*sm == 0) *sm = 1;
+    }
+    if constexpr (NARROW) {
+        // Every row has at most UNROLL entries (the graph's maximum degree; a grid's rows): each
+        // lane relaxes its own row, entry i in step i, with no prefix sum and no search for the owner.
+        if (__ballot(deg != 0) == 0) return;
+        bool valid[UNROLL];
+        uint32_t sl[UNROLL], uu[UNROLL], ww[UNROLL];
+        uint64_t ks[UNROLL];
+#pragma unroll
+        for (int i = 0; i < UNROLL; i++) {
+            valid[i] = (uint32_t)i < deg;
+            const uint2 a = P.g.adj[valid[i] ? beg + (uint32_t)i : 0u];
+            uu[i] = valid[i] ? a.x : 0u;
+            ww[i] = a.y;
+            if (P.split) valid[i] = valid[i] && (heavy ? a.y > P.delta : a.y <= P.delta);
+            sl[i] = slot;
+            ks[i] = kv;
+        }
+        relax_multi(P, R, thr, valid, sl, ks, uu, ww, L, use_lq, lq_head, lq_tail);
+        return;
     }
     const uint32_t incl = wave_incl_scan(deg);
     const uint32_t total = __shfl(incl, 63, 64);
@@ -372,51 +394,61 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
     }
 }
 
-// The 64 smallest-distance entries of the local queue's cnt > 64 entries at
-// ring positions [h, h + cnt) are returned in the lanes' registers; the others
-// move to [h + 64, h + cnt).  The sort key is the distance, clamped, with the
-// ring position below it, so the keys are distinct: a radix search over the
-// key bits (two ballots per bit) finds the 64th smallest, and ballot prefixes
-// place the selected entries (one per lane, through LDS) and the rest.  Order
-// only steers the work, never the result.
+// A monotone 16-bit compression of a distance (a 5-bit exponent over an
+// 11-bit mantissa; exact below 2048, relative step 2^-11 above): the local
+// queue's order only needs nearly-smallest-first.
+DEVI uint32_t order_key(uint32_t d) {
+    if (d < 2048u) return d;
+    const uint32_t t = 31u - (uint32_t)__builtin_clz(d);  // 11..31
+    return ((t - 10u) << 11) | ((d >> (t - 11u)) & 0x7FFu);
+}
+
+// The 64 entries of smallest order key among the local queue's cnt > 64
+// entries at ring positions [h, h + cnt) (equal keys in position order) are
+// returned in the lanes' registers; the others move to [h + 64, h + cnt).  A
+// radix search over the 16 key bits (two ballots per bit) finds the 64th
+// smallest key x; the entries below x and the first ones equal to it are
+// placed by ballot prefixes (one per lane, through LDS), and so is the rest.
+// Order only steers the work, never the result.
 DEVI void lq_select(WaveScratch *L, uint32_t h, uint32_t cnt, uint64_t &item, uint64_t &kv, uint32_t &beg,
                     uint32_t &deg) {
     const uint32_t ln = lane();
-    uint32_t a[2];
+    constexpr uint32_t NONE = 1u << 16;  // above every order key
+    uint32_t a[2], p[2];
 #pragma unroll
     for (int j = 0; j < 2; j++) {
         const uint32_t i = ln + 64 * j;
-        a[j] = 0xFFFFFFFFu;
-        if (i < cnt) {
-            const uint32_t pos = (h + i) % LQ_CAP;
-            const uint32_t d = (uint32_t)(L->lq_key[pos] >> 32);
-            a[j] = (min(d, (1u << 25) - 2) << 7) | pos;
-        }
+        p[j] = (h + i) % LQ_CAP;
+        a[j] = i < cnt ? order_key((uint32_t)(L->lq_key[p[j]] >> 32)) : NONE;
     }
     uint32_t x = 0;  // the largest value with at most 63 keys below it: the 64th smallest key
 #pragma unroll
-    for (int bit = 31; bit >= 0; bit--) {
+    for (int bit = 15; bit >= 0; bit--) {
         const uint32_t y = x | (1u << bit);
         const uint32_t below = (uint32_t)__popcll(__ballot(a[0] < y)) + (uint32_t)__popcll(__ballot(a[1] < y));
         x = below <= 63 ? y : x;
     }
-    const bool s0 = a[0] <= x, s1 = a[1] <= x;
-    const bool q0 = !s0 && a[0] != 0xFFFFFFFFu, q1 = !s1 && a[1] != 0xFFFFFFFFu;
+    // fewer than 64 keys lie below x and at least 64 at or below it: the first `need` equal ones join
+    const uint64_t b0 = __ballot(a[0] < x), b1 = __ballot(a[1] < x);
+    const uint64_t e0 = __ballot(a[0] == x), e1 = __ballot(a[1] == x);
+    const uint32_t need = 64u - (uint32_t)__popcll(b0) - (uint32_t)__popcll(b1);
+    const bool s0 = a[0] < x || (a[0] == x && lanes_below(e0) < need);
+    const bool s1 = a[1] < x || (a[1] == x && (uint32_t)__popcll(e0) + lanes_below(e1) < need);
+    const bool q0 = !s0 && a[0] != NONE, q1 = !s1 && a[1] != NONE;
     const uint64_t m0 = __ballot(s0), m1 = __ballot(s1), n0 = __ballot(q0), n1 = __ballot(q1);
     uint32_t *slot = L->incl;  // free until the expansion rebuilds it
-    if (s0) slot[lanes_below(m0)] = a[0] & (LQ_CAP - 1);
-    if (s1) slot[(uint32_t)__popcll(m0) + lanes_below(m1)] = a[1] & (LQ_CAP - 1);
+    if (s0) slot[lanes_below(m0)] = p[0];
+    if (s1) slot[(uint32_t)__popcll(m0) + lanes_below(m1)] = p[1];
     // the rest: every entry is read before any is written
     uint64_t r_item[2] = {0, 0}, r_key[2] = {0, 0};
     uint32_t r_beg[2] = {0, 0}, r_deg[2] = {0, 0};
 #pragma unroll
     for (int j = 0; j < 2; j++) {
         if (j ? q1 : q0) {
-            const uint32_t p = a[j] & (LQ_CAP - 1);
-            r_item[j] = L->lq_item[p];
-            r_key[j] = L->lq_key[p];
-            r_beg[j] = L->lq_beg[p];
-            r_deg[j] = L->lq_deg[p];
+            r_item[j] = L->lq_item[p[j]];
+            r_key[j] = L->lq_key[p[j]];
+            r_beg[j] = L->lq_beg[p[j]];
+            r_deg[j] = L->lq_deg[p[j]];
         }
     }
     wave_sync();
@@ -443,6 +475,7 @@ DEVI void lq_select(WaveScratch *L, uint32_t h, uint32_t cnt, uint64_t &item, ui
 // entry carries the key it was improved to: a later improvement of the same
 // vertex queues or lists it again), then move what is left to the next
 // round's list (once per vertex per round; that path re-reads the key).
+template <bool NARROW>
 DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr, WaveScratch *L, uint32_t budget,
                       uint32_t &h, uint32_t &t) {
     for (uint32_t it = 0; it < budget && h != t; it++) {
@@ -467,7 +500,7 @@ DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr
                 kv = KEY_INF;
             }
         }
-        expand_items(P, R, thr, s_slot(item), (uint32_t)item, kv, beg, deg, false, L, true, h, t);
+        expand_items<NARROW>(P, R, thr, s_slot(item), (uint32_t)item, kv, beg, deg, false, L, true, h, t);
     }
     while (h != t) {
         const uint32_t take = min(t - h, 64u);
@@ -488,6 +521,7 @@ DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr
     }
 }
 
+template <bool NARROW>
 DEVI void relax_round_body(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t cs, uint32_t cb,
                            WaveScratch *L, uint32_t wave_gid, uint32_t nwaves) {
     const uint32_t ng = (cs + 63) / 64;
@@ -514,11 +548,11 @@ DEVI void relax_round_body(const VorParams &P, const RoundIdx &R, const uint64_t
                 beg = P.g.rp[v];
                 deg = kv == KEY_INF ? 0 : P.g.rp[v + 1] - beg;
             }
-            expand_items(P, R, thr, slot, v, kv, beg, deg, heavy, L, use_lq, h, t);
+            expand_items<NARROW>(P, R, thr, slot, v, kv, beg, deg, heavy, L, use_lq, h, t);
         } else {
             process_b_chunk(P, R, thr, u - ng, L, use_lq, h, t);
         }
-        if (use_lq) drain_local(P, R, thr, L, P.local_iters, h, t);
+        if (use_lq) drain_local<NARROW>(P, R, thr, L, P.local_iters, h, t);
         flush_out(P, R, L);
     }
     if (P.counting && lane() < EV_N) {
@@ -622,6 +656,7 @@ DEVI void advance_body(const VorParams &P, const uint64_t *thr, const uint64_t *
 // round's list, and, in the last workgroup to finish, the bucket decision.
 // 256-thread workgroups (the host clamps the block size); the default grid is
 // as many workgroups as fit on the device at once (round_max_grid).
+template <bool NARROW>
 __global__ void __launch_bounds__(256) k_round(VorParams P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     WaveScratch *s_wave = (WaveScratch *)dyn_smem;
@@ -635,7 +670,7 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
         advance_body(P, P.slot.thr, P.slot.thr_prev, P.slot.adv, r + 1, R.nxt, R.c_nxt, R.b, (int)R.b, wave_gid,
                      nwaves, &s_wave[w]);
     const uint32_t cs = min(ld_agent(&P.cnt->s[r % 3u]), P.cap_s), cb = min(ld_agent(&P.cnt->b[r % 3u]), P.cap_b);
-    relax_round_body(P, R, P.slot.thr, cs, cb, &s_wave[w], wave_gid, nwaves);
+    relax_round_body<NARROW>(P, R, P.slot.thr, cs, cb, &s_wave[w], wave_gid, nwaves);
 
     __syncthreads();
     if (threadIdx.x == 0) {  // the last workgroup of its group, then the last group, takes the decision
@@ -740,7 +775,7 @@ __global__ void __launch_bounds__(256) k_persistent(VorParams P, uint32_t max_ro
         const RoundIdx R = round_idx(r);
         const uint32_t cs = min(ld_agent(&P.cnt->s[r % 3u]), P.cap_s);
         const uint32_t cb = min(ld_agent(&P.cnt->b[r % 3u]), P.cap_b);
-        relax_round_body(P, R, s_thr, cs, cb, &s_wave[w], wave_gid, nwaves);
+        relax_round_body<false>(P, R, s_thr, cs, cb, &s_wave[w], wave_gid, nwaves);
         if (blockIdx.x == 0) {
             const uint32_t nb = (r + 1) % 3u;
             for (uint32_t q = threadIdx.x; q < ns; q += blockDim.x) {
@@ -1786,7 +1821,10 @@ hipError_t launch_slot_start(const VorParams &P, uint32_t slot, const uint32_t *
 static size_t wave_smem(uint32_t block) { return (size_t)(block / 64) * sizeof(WaveScratch); }
 
 hipError_t launch_round(const VorParams &P, uint32_t grid, uint32_t block, hipStream_t s) {
-    hipLaunchKernelGGL(k_round, dim3(grid), dim3(block), wave_smem(block), s, P);
+    if (P.g.max_deg <= (uint32_t)UNROLL)
+        hipLaunchKernelGGL(k_round<true>, dim3(grid), dim3(block), wave_smem(block), s, P);
+    else
+        hipLaunchKernelGGL(k_round<false>, dim3(grid), dim3(block), wave_smem(block), s, P);
     return hipGetLastError();
 }
 
@@ -1812,7 +1850,7 @@ int round_max_grid(uint32_t block) {
     int dev = 0, per_cu = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round, (int)block, wave_smem(block)) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round<false>, (int)block, wave_smem(block)) != hipSuccess)
         return 0;
     return per_cu * prop.multiProcessorCount;
 }
