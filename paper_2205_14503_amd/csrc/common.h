@@ -72,10 +72,17 @@ struct Counters {
 constexpr uint32_t ROUND_GROUPS = 8;
 enum { EV_ATTEMPT = 0, EV_ATOMIC, EV_IMPROVED, EV_LOCAL, EV_GLOBAL, EV_PARK, EV_ITEMS, EV_N };
 
+constexpr uint32_t ELL_W = 4;
+constexpr uint32_t ELL_NONE = 0xFFFFFFFFu;
+
 struct DevGraph {
     uint32_t n;
     uint32_t nnz;
     uint32_t max_deg;     // largest row (clamped to 2^32 - 1)
+    // Graphs whose rows have at most ELL_W entries also hold them at a fixed
+    // stride: row v is ell[2v], ell[2v + 1], each the (col, w) pairs of two
+    // entries in CSR order, col = ELL_NONE past the row's end.  Null otherwise.
+    const uint4 *ell;
     const uint32_t *rp;   // row offsets, n+1 (32-bit: nnz < 2^32)
     const uint2 *adj;     // (col, w) per CSR entry
     // Rows of degree > scan_heavy are split into chunks of scan_chunk edges

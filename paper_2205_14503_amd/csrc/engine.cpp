@@ -212,6 +212,21 @@ static __global__ void k_convert(const uint64_t *rp64, uint32_t n, const uint32_
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) adj[e] = make_uint2(col[e], w[e]);
 }
 
+// Fixed-stride copy of a CSR whose rows have at most ELL_W = 4 entries.
+static __global__ void k_build_ell(const uint32_t *rp, const uint2 *adj, uint32_t n, uint4 *ell) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint32_t beg = rp[v], deg = rp[v + 1] - beg;
+        uint32_t c[ELL_W], w[ELL_W];
+        for (uint32_t i = 0; i < ELL_W; i++) {
+            c[i] = i < deg ? adj[beg + i].x : ELL_NONE;
+            w[i] = i < deg ? adj[beg + i].y : 0u;
+        }
+        ell[2 * v] = make_uint4(c[0], w[0], c[1], w[1]);
+        ell[2 * v + 1] = make_uint4(c[2], w[2], c[3], w[3]);
+    }
+}
+
 static __global__ void k_weight_sum(const uint32_t *w, uint64_t nnz, unsigned long long *sum) {
     unsigned long long s = 0;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (uint64_t)gridDim.x * blockDim.x) s += w[e];
@@ -571,12 +586,19 @@ static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t
         (void)hipMemcpyAsync(g->d_heavy_rows, hrows.data(), hrows.size() * 4, hipMemcpyHostToDevice, s);
     (void)hipMemcpyAsync(g->d_heavy_off, hoff.data(), hoff.size() * 4, hipMemcpyHostToDevice, s);
     if ((rc = hip_check(hipStreamSynchronize(s), "heavy rows"))) return rc;
+    if (n && g->max_deg <= ELL_W) {
+        if ((rc = dev_alloc((void **)&g->d_ell, (size_t)n * 2 * sizeof(uint4)))) return rc;
+        hipLaunchKernelGGL(k_build_ell, dim3(4096), dim3(256), 0, s, g->d_rp, g->d_adj, n, g->d_ell);
+        if ((rc = hip_check(hipGetLastError(), "fixed-stride rows"))) return rc;
+        if ((rc = hip_check(hipStreamSynchronize(s), "fixed-stride rows"))) return rc;
+    }
     DevGraph &dg = g->dg;
     dg.n = n;
     dg.nnz = (uint32_t)nnz;
     dg.max_deg = (uint32_t)std::min<uint64_t>(g->max_deg, 0xFFFFFFFFull);
     dg.rp = g->d_rp;
     dg.adj = g->d_adj;
+    dg.ell = g->d_ell;
     dg.nheavy = g->nheavy;
     dg.nheavy_chunks = hoff.back();
     dg.heavy_rows = g->d_heavy_rows;
@@ -675,6 +697,7 @@ extern "C" int steiner_graph_free(steiner_graph *g) {
     g->clusters.release();
     dev_free(g->d_rp);
     dev_free(g->d_adj);
+    dev_free(g->d_ell);
     dev_free(g->d_heavy_rows);
     dev_free(g->d_heavy_off);
     dev_free(g->d_perm);

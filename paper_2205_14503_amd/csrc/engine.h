@@ -149,6 +149,7 @@ struct steiner_graph {
     uint64_t nnz = 0;
     uint32_t *d_rp = nullptr;
     uint2 *d_adj = nullptr;
+    uint4 *d_ell = nullptr;  // fixed-stride rows when every row has at most ELL_W entries
     uint32_t *d_heavy_rows = nullptr, *d_heavy_off = nullptr;
     uint32_t nheavy = 0;
     uint64_t max_deg = 0;

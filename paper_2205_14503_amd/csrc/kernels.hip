@@ -120,6 +120,7 @@ DEVI void append_b(const VorParams &P, uint32_t list, uint32_t cidx, bool pred, 
 // hop).  Anything the queue cannot hold goes to the next round's list.
 constexpr uint32_t LQ_CAP = 128;
 constexpr uint32_t OUT_CAP = 128;
+constexpr uint32_t PEND_CAP = 256;
 static_assert(LQ_CAP == 128, "lq_select holds two queue entries per lane");
 
 struct WaveScratch {
@@ -137,6 +138,10 @@ struct WaveScratch {
     // instead of one per 64-edge step (the list counter is a single address)
     uint64_t out[OUT_CAP];
     uint32_t out_n;
+    // fixed-stride rows: improved vertices the local queue could not hold,
+    // claimed for the next round's list together at the end of the unit
+    uint64_t pend[PEND_CAP];
+    uint32_t pend_n;
     uint32_t ev[EV_N];  // per-wave event counts (counting mode)
 };
 
@@ -238,6 +243,7 @@ DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr
             if (nd < *fm) atomicMin(fm, nd);
         }
     }
+    bool spill[UNROLL];  // near but not queued locally: claim for the next round's list
 #pragma unroll
     for (int i = 0; i < UNROLL; i++) {
         deg[i] -= beg[i];
@@ -262,13 +268,24 @@ DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr
         count(P, Lw, EV_IMPROVED, tried[i]);
         count(P, Lw, EV_LOCAL, local);
         count(P, Lw, EV_PARK, tried[i] && !near[i]);
-        bool claim = false;
-        if (near[i] && !local) {
-            if (atomicExch(P.aux + (size_t)slot[i] * n + u[i], R.r + 1) != R.r + 1) {
-                claim = true;
-                uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + slot[i];
-                if (*nm == 0) *nm = 1;
-            }
+        spill[i] = near[i] && !local;
+    }
+    // the claims of all steps are in flight together: the returned stamps are used only after the
+    // last one is issued (an empty asm hides them from the compiler until then)
+    uint32_t old[UNROLL];
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        old[i] = R.r + 1;
+        if (spill[i]) old[i] = atomicExch(P.aux + (size_t)slot[i] * n + u[i], R.r + 1);
+    }
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) asm volatile("" : "+v"(old[i]));
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        const bool claim = spill[i] && old[i] != R.r + 1;
+        if (claim) {
+            uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + slot[i];
+            if (*nm == 0) *nm = 1;
         }
         count(P, Lw, EV_GLOBAL, claim);
         stage_s(P, R, Lw, claim && deg[i] <= P.small_max, s_item(slot[i], u[i]));
@@ -279,9 +296,7 @@ DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr
 // Expands one frontier item per lane: the row [beg, beg + deg) of a vertex
 // with key kv in query `slot` (deg = 0 for idle lanes), 64 * UNROLL edges per
 // step, balanced across the wave by a prefix sum of the degrees (coalesced
-// 8-byte (col, w) loads within each row).  NARROW: no row has more than
-// UNROLL entries.
-template <bool NARROW>
+// 8-byte (col, w) loads within each row).
 DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t slot, uint32_t v,
                        uint64_t kv, uint32_t beg, uint32_t deg, bool heavy, WaveScratch *L, bool use_lq,
                        uint32_t &lq_head, uint32_t &lq_tail) {
@@ -291,26 +306,6 @@ DEVI void expand_items(const VorParams &P, const RoundIdx &R, const uint64_t *th
         P.settled[(size_t)slot * P.g.n + v] = 1;
         uint32_t *sm = P.settle_mark + (size_t)R.b * P.nslots + slot;
         if (*sm == 0) *sm = 1;
-    }
-    if constexpr (NARROW) {
-        // Every row has at most UNROLL entries (the graph's maximum degree; a grid's rows): each
-        // lane relaxes its own row, entry i in step i, with no prefix sum and no search for the owner.
-        if (__ballot(deg != 0) == 0) return;
-        bool valid[UNROLL];
-        uint32_t sl[UNROLL], uu[UNROLL], ww[UNROLL];
-        uint64_t ks[UNROLL];
-#pragma unroll
-        for (int i = 0; i < UNROLL; i++) {
-            valid[i] = (uint32_t)i < deg;
-            const uint2 a = P.g.adj[valid[i] ? beg + (uint32_t)i : 0u];
-            uu[i] = valid[i] ? a.x : 0u;
-            ww[i] = a.y;
-            if (P.split) valid[i] = valid[i] && (heavy ? a.y > P.delta : a.y <= P.delta);
-            sl[i] = slot;
-            ks[i] = kv;
-        }
-        relax_multi(P, R, thr, valid, sl, ks, uu, ww, L, use_lq, lq_head, lq_tail);
-        return;
     }
     const uint32_t incl = wave_incl_scan(deg);
     const uint32_t total = __shfl(incl, 63, 64);
@@ -475,7 +470,6 @@ DEVI void lq_select(WaveScratch *L, uint32_t h, uint32_t cnt, uint64_t &item, ui
 // entry carries the key it was improved to: a later improvement of the same
 // vertex queues or lists it again), then move what is left to the next
 // round's list (once per vertex per round; that path re-reads the key).
-template <bool NARROW>
 DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr, WaveScratch *L, uint32_t budget,
                       uint32_t &h, uint32_t &t) {
     for (uint32_t it = 0; it < budget && h != t; it++) {
@@ -500,7 +494,7 @@ DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr
                 kv = KEY_INF;
             }
         }
-        expand_items<NARROW>(P, R, thr, s_slot(item), (uint32_t)item, kv, beg, deg, false, L, true, h, t);
+        expand_items(P, R, thr, s_slot(item), (uint32_t)item, kv, beg, deg, false, L, true, h, t);
     }
     while (h != t) {
         const uint32_t take = min(t - h, 64u);
@@ -521,6 +515,194 @@ DEVI void drain_local(const VorParams &P, const RoundIdx &R, const uint64_t *thr
     }
 }
 
+
+// ------------------------------------------- rows of at most ELL_W entries
+//
+// On a graph whose rows all fit the fixed-stride copy (a grid), a hop of the
+// local queue is a chain of dependent device-memory accesses, so this path
+// keeps it short: a row's address follows from the vertex id (no row-offset
+// read), the superseded test reads the key together with the row, and the
+// claims of spilled vertices wait until the end of the unit.
+
+static_assert(UNROLL == (int)ELL_W, "one step per fixed-stride row entry");
+
+// Claims the wave's pending spilled items for the next round's list (once per
+// vertex per round, stamp R.r + 1), UNROLL exchanges per lane in flight, and
+// stages the claimed ones.
+DEVI void claim_pending(const VorParams &P, const RoundIdx &R, WaveScratch *L) {
+    wave_sync();
+    const uint32_t cnt = L->pend_n;
+    const uint32_t n = P.g.n;
+    for (uint32_t base = 0; base < cnt; base += 64 * UNROLL) {
+        uint64_t it[UNROLL];
+        uint32_t old[UNROLL];
+        bool has[UNROLL];
+#pragma unroll
+        for (int j = 0; j < UNROLL; j++) {
+            const uint32_t idx = base + 64 * j + lane();
+            has[j] = idx < cnt;
+            it[j] = has[j] ? L->pend[idx] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < UNROLL; j++) {
+            old[j] = R.r + 1;
+            if (has[j]) old[j] = atomicExch(P.aux + (size_t)s_slot(it[j]) * n + (uint32_t)it[j], R.r + 1);
+        }
+#pragma unroll
+        for (int j = 0; j < UNROLL; j++) asm volatile("" : "+v"(old[j]));  // all exchanges issued first
+#pragma unroll
+        for (int j = 0; j < UNROLL; j++) {
+            const bool claim = has[j] && old[j] != R.r + 1;
+            if (claim) {
+                uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + s_slot(it[j]);
+                if (*nm == 0) *nm = 1;
+            }
+            count(P, L, EV_GLOBAL, claim);
+            stage_s(P, R, L, claim, it[j]);
+        }
+    }
+    wave_sync();
+    if (lane() == 0) L->pend_n = 0;
+    wave_sync();
+}
+
+// Adds the items of the lanes with `pred` to the pending claims.
+DEVI void pend_items(const VorParams &P, const RoundIdx &R, WaveScratch *L, bool pred, uint64_t item) {
+    const uint64_t m = __ballot(pred);
+    if (m == 0) return;
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    wave_sync();
+    if (L->pend_n + cnt > PEND_CAP) claim_pending(P, R, L);
+    const uint32_t at = L->pend_n;
+    if (pred) L->pend[at + lanes_below(m)] = item;
+    wave_sync();
+    if (lane() == 0) L->pend_n = at + cnt;
+    wave_sync();
+}
+
+// relax_multi for one fixed-stride row per lane (source key ksrc of query
+// slot; step i relaxes entry i): improved targets inside the bucket go to the
+// local queue (key only: the row needs no extent) or, when it is full (or
+// unused), to the pending claims; the others are parked.
+DEVI void relax_narrow(const VorParams &P, const RoundIdx &R, const uint64_t *thr, const bool *valid,
+                       uint32_t slot, uint64_t ksrc, const uint32_t *u, const uint32_t *w, WaveScratch *L,
+                       bool use_lq, uint32_t &lq_head, uint32_t &lq_tail) {
+    const uint32_t n = P.g.n;
+    const uint32_t tv = (uint32_t)min(thr[slot], (uint64_t)DIST_INF);
+    uint64_t cand[UNROLL], cur[UNROLL];
+    bool live[UNROLL], tried[UNROLL], near[UNROLL];
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        const uint64_t d = (ksrc >> 32) + (uint64_t)w[i];
+        live[i] = valid[i] && d < DIST_INF;
+        cand[i] = (d << 32) | (ksrc & 0xFFFFFFFFull);
+    }
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++)  // possibly stale (larger) values: filter only
+        cur[i] = P.key[(size_t)slot * n + (live[i] ? u[i] : 0u)];
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        tried[i] = live[i] && cand[i] < cur[i];
+        near[i] = tried[i] && (uint32_t)(cand[i] >> 32) < tv;
+        count(P, L, EV_ATTEMPT, valid[i]);
+        count(P, L, EV_ATOMIC, tried[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++)
+        if (tried[i]) (void)atomicMin((unsigned long long *)(P.key + (size_t)slot * n + u[i]), (unsigned long long)cand[i]);
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        if (tried[i] && !near[i]) {  // park until the query's bucket reaches it
+            P.dirty[(size_t)slot * n + u[i]] = 1;
+            uint32_t *fm = P.far_min + (size_t)R.b * P.nslots + slot;
+            const uint32_t nd = (uint32_t)(cand[i] >> 32);
+            if (nd < *fm) atomicMin(fm, nd);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        bool local = false;
+        if (use_lq) {
+            const uint64_t m = __ballot(near[i]);
+            if (m) {
+                const uint32_t space = LQ_CAP - (lq_tail - lq_head);
+                const uint32_t rank = lanes_below(m);
+                local = near[i] && rank < space;
+                if (local) {
+                    const uint32_t at = (lq_tail + rank) % LQ_CAP;
+                    L->lq_item[at] = s_item(slot, u[i]);
+                    L->lq_key[at] = cand[i];
+                }
+                lq_tail += min((uint32_t)__popcll(m), space);
+            }
+        }
+        count(P, L, EV_IMPROVED, tried[i]);
+        count(P, L, EV_LOCAL, local);
+        count(P, L, EV_PARK, tried[i] && !near[i]);
+        pend_items(P, R, L, near[i] && !local, s_item(slot, u[i]));
+    }
+}
+
+// Expands one fixed-stride row per lane (vertex v of query slot with key kv;
+// lanes with `active` false do nothing).  check_sup: the items come from the
+// local queue with the key they were queued with, and one whose vertex has
+// been improved since is skipped (its key is read together with the row).
+DEVI void expand_narrow(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t slot, uint32_t v,
+                        uint64_t kv, bool active, bool heavy, WaveScratch *L, bool use_lq, uint32_t &lq_head,
+                        uint32_t &lq_tail, bool check_sup) {
+    if (__ballot(active) == 0) return;
+    uint64_t now = KEY_INF;
+    if (check_sup) now = ld_agent(P.key + (size_t)slot * P.g.n + v);
+    const uint4 r0 = P.g.ell[2 * (size_t)v], r1 = P.g.ell[2 * (size_t)v + 1];
+    const uint32_t col[UNROLL] = {r0.x, r0.z, r1.x, r1.z}, wt[UNROLL] = {r0.y, r0.w, r1.y, r1.w};
+    const bool on = active && kv != KEY_INF && !(check_sup && (P.lq_mode & 2u) && now < kv);
+    count(P, L, EV_ITEMS, on);
+    if (P.split && !heavy && on) {  // its heavy edges wait until the bucket closes
+        P.settled[(size_t)slot * P.g.n + v] = 1;
+        uint32_t *sm = P.settle_mark + (size_t)R.b * P.nslots + slot;
+        if (*sm == 0) *sm = 1;
+    }
+    bool valid[UNROLL];
+    uint32_t uu[UNROLL];
+#pragma unroll
+    for (int i = 0; i < UNROLL; i++) {
+        valid[i] = on && col[i] != ELL_NONE;
+        if (P.split) valid[i] = valid[i] && (heavy ? wt[i] > P.delta : wt[i] <= P.delta);
+        uu[i] = valid[i] ? col[i] : 0u;
+    }
+    relax_narrow(P, R, thr, valid, slot, kv, uu, wt, L, use_lq, lq_head, lq_tail);
+}
+
+// drain_local for fixed-stride rows: up to `budget` batches of 64, smallest
+// first; what is left joins the pending claims, which are then made.
+DEVI void drain_narrow(const VorParams &P, const RoundIdx &R, const uint64_t *thr, WaveScratch *L, uint32_t budget,
+                       uint32_t &h, uint32_t &t) {
+    for (uint32_t it = 0; it < budget && h != t; it++) {
+        const uint32_t cnt = t - h;
+        const uint32_t take = min(cnt, 64u);
+        wave_sync();
+        uint64_t item = 0, kv = KEY_INF;
+        if ((P.lq_mode & 1u) && cnt > 64) {
+            uint32_t beg_unused, deg_unused;
+            lq_select(L, h, cnt, item, kv, beg_unused, deg_unused);
+        } else if (lane() < take) {
+            const uint32_t at = (h + lane()) % LQ_CAP;
+            item = L->lq_item[at];
+            kv = L->lq_key[at];
+        }
+        h += take;
+        expand_narrow(P, R, thr, s_slot(item), (uint32_t)item, kv, lane() < take, false, L, true, h, t, true);
+    }
+    while (h != t) {
+        const uint32_t take = min(t - h, 64u);
+        wave_sync();
+        const bool has = lane() < take;
+        const uint64_t item = has ? L->lq_item[(h + lane()) % LQ_CAP] : 0;
+        h += take;
+        pend_items(P, R, L, has, item);
+    }
+}
+
 template <bool NARROW>
 DEVI void relax_round_body(const VorParams &P, const RoundIdx &R, const uint64_t *thr, uint32_t cs, uint32_t cb,
                            WaveScratch *L, uint32_t wave_gid, uint32_t nwaves) {
@@ -529,14 +711,15 @@ DEVI void relax_round_body(const VorParams &P, const RoundIdx &R, const uint64_t
     const bool use_lq = P.local_iters != 0;
     if (lane() == 0) {
         L->out_n = 0;
+        L->pend_n = 0;
         for (int i = 0; i < EV_N; i++) L->ev[i] = 0;
     }
     wave_sync();
     for (uint32_t u = wave_gid; u < units; u += nwaves) {
         uint32_t h = 0, t = 0;
-        if (u < ng) {
+        if (NARROW && u < ng) {  // rows of at most ELL_W entries: every item is a small row
             const uint32_t idx = u * 64 + lane();
-            uint32_t slot = 0, beg = 0, deg = 0, v = 0;
+            uint32_t slot = 0, v = 0;
             uint64_t kv = KEY_INF;
             bool heavy = false;
             if (idx < cs) {
@@ -545,14 +728,31 @@ DEVI void relax_round_body(const VorParams &P, const RoundIdx &R, const uint64_t
                 heavy = s_heavy(it);
                 v = (uint32_t)it;
                 kv = ld_agent(P.key + (size_t)slot * P.g.n + v);
-                beg = P.g.rp[v];
-                deg = kv == KEY_INF ? 0 : P.g.rp[v + 1] - beg;
             }
-            expand_items<NARROW>(P, R, thr, slot, v, kv, beg, deg, heavy, L, use_lq, h, t);
+            expand_narrow(P, R, thr, slot, v, kv, idx < cs, heavy, L, use_lq, h, t, false);
+            if (use_lq) drain_narrow(P, R, thr, L, P.local_iters, h, t);
+            claim_pending(P, R, L);
         } else {
-            process_b_chunk(P, R, thr, u - ng, L, use_lq, h, t);
+            if (u < ng) {
+                const uint32_t idx = u * 64 + lane();
+                uint32_t slot = 0, beg = 0, deg = 0, v = 0;
+                uint64_t kv = KEY_INF;
+                bool heavy = false;
+                if (idx < cs) {
+                    const uint64_t it = P.items_s[R.cur][idx];
+                    slot = s_slot(it);
+                    heavy = s_heavy(it);
+                    v = (uint32_t)it;
+                    kv = ld_agent(P.key + (size_t)slot * P.g.n + v);
+                    beg = P.g.rp[v];
+                    deg = kv == KEY_INF ? 0 : P.g.rp[v + 1] - beg;
+                }
+                expand_items(P, R, thr, slot, v, kv, beg, deg, heavy, L, use_lq, h, t);
+            } else {
+                process_b_chunk(P, R, thr, u - ng, L, use_lq, h, t);
+            }
+            if (use_lq) drain_local(P, R, thr, L, P.local_iters, h, t);
         }
-        if (use_lq) drain_local<NARROW>(P, R, thr, L, P.local_iters, h, t);
         flush_out(P, R, L);
     }
     if (P.counting && lane() < EV_N) {
@@ -1821,7 +2021,8 @@ hipError_t launch_slot_start(const VorParams &P, uint32_t slot, const uint32_t *
 static size_t wave_smem(uint32_t block) { return (size_t)(block / 64) * sizeof(WaveScratch); }
 
 hipError_t launch_round(const VorParams &P, uint32_t grid, uint32_t block, hipStream_t s) {
-    if (P.g.max_deg <= (uint32_t)UNROLL)
+    // fixed-stride rows, all of them within the local queue's size limit (no chunked rows)
+    if (P.g.ell && P.g.max_deg <= min(ELL_W, P.small_max))
         hipLaunchKernelGGL(k_round<true>, dim3(grid), dim3(block), wave_smem(block), s, P);
     else
         hipLaunchKernelGGL(k_round<false>, dim3(grid), dim3(block), wave_smem(block), s, P);

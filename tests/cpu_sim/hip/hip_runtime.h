@@ -25,6 +25,10 @@ struct uint2 {
     uint32_t x, y;
 };
 inline uint2 make_uint2(uint32_t a, uint32_t b) { return uint2{a, b}; }
+struct uint4 {
+    uint32_t x, y, z, w;
+};
+inline uint4 make_uint4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) { return uint4{a, b, c, d}; }
 
 extern thread_local dim3 blockIdx, threadIdx, blockDim, gridDim;
 
