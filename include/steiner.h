@@ -142,7 +142,7 @@ int steiner_graph_upload_device(uint32_t n, uint64_t nnz, const void *d_row_ptr,
 int steiner_graph_free(steiner_graph *g);
 
 /* Autotuner: times a small set of relaxation settings (bucket width, depth of
- * the wave-local queue, workgroups of a one-query pass) on the given sample
+ * the wave-local queue, workgroups of a host-stepped pass) on the given sample
  * seed set and keeps the fastest as
  * this graph's defaults for every later call that passes NULL options or zero
  * fields.  Results never depend on the choice.  out (optional) receives the

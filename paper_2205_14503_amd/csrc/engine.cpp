@@ -154,8 +154,8 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
     while ((g->max_deg + r.chunk - 1) / r.chunk >= (1ull << CHUNK_BITS)) r.chunk *= 2;  // chunk index field
     // host-stepped: as many workgroups as are resident at once (the round kernel's occupancy);
     // persistent: two per CU at most, the co-residency its grid barrier needs
-    // one-query passes of the host-stepped driver use the tuned count, a latency-bound pass often runs
-    // faster on fewer workgroups; batches and the server keep every resident one
+    // passes of the host-stepped driver use the tuned count (a latency-bound graph often runs faster on
+    // fewer workgroups, batches of its queries too); the server keeps every resident one
     const bool given = r.grid != 0;
     if (!given) {
         if (r.driver == 2) {
@@ -165,8 +165,8 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
             r.grid = resident > 0 ? (uint32_t)resident : (uint32_t)std::max(1, g->cu_count) * 4u;
         }
     }
-    r.grid_one = r.grid;
-    if (!given && r.driver != 2 && g->tuned_grid && g->tuned_grid <= r.grid && r.block == 256) r.grid_one = g->tuned_grid;
+    r.grid_tuned = r.grid;
+    if (!given && r.driver != 2 && g->tuned_grid && g->tuned_grid <= r.grid && r.block == 256) r.grid_tuned = g->tuned_grid;
     return r;
 }
 
@@ -836,7 +836,7 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
         o.local_iters = l;
         o.split = split != 0 && d != 0xFFFFFFFFu;
         o.lazy_pred = lazy;
-        if (grid) o.grid = o.grid_one = grid;
+        if (grid) o.grid = o.grid_tuned = grid;
         double t_min = 1e300;
         for (int rep = 0; rep < 2; rep++) {
             std::vector<Query> qs(1);

@@ -553,10 +553,7 @@ DEVI void claim_pending(const VorParams &P, const RoundIdx &R, WaveScratch *L) {
 #pragma unroll
         for (int j = 0; j < UNROLL; j++) {
             const bool claim = has[j] && old[j] != R.r + 1;
-            if (claim) {
-                uint32_t *nm = P.near_mark + (size_t)R.b * P.nslots + s_slot(it[j]);
-                if (*nm == 0) *nm = 1;
-            }
+            if (claim) P.near_mark[(size_t)R.b * P.nslots + s_slot(it[j])] = 1;  // no read: off the chain
             count(P, L, EV_GLOBAL, claim);
             stage_s(P, R, L, claim, it[j]);
         }
@@ -651,8 +648,9 @@ DEVI void expand_narrow(const VorParams &P, const RoundIdx &R, const uint64_t *t
                         uint64_t kv, bool active, bool heavy, WaveScratch *L, bool use_lq, uint32_t &lq_head,
                         uint32_t &lq_tail, bool check_sup) {
     if (__ballot(active) == 0) return;
+    // a plain read: a stale value is never below the current key, so it can only miss a skip
     uint64_t now = KEY_INF;
-    if (check_sup) now = ld_agent(P.key + (size_t)slot * P.g.n + v);
+    if (check_sup) now = P.key[(size_t)slot * P.g.n + v];
     const uint4 r0 = P.g.ell[2 * (size_t)v], r1 = P.g.ell[2 * (size_t)v + 1];
     const uint32_t col[UNROLL] = {r0.x, r0.z, r1.x, r1.z}, wt[UNROLL] = {r0.y, r0.w, r1.y, r1.w};
     const bool on = active && kv != KEY_INF && !(check_sup && (P.lq_mode & 2u) && now < kv);
@@ -861,15 +859,28 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     WaveScratch *s_wave = (WaveScratch *)dyn_smem;
     __shared__ int s_last, s_adv, s_act;
-    if (ld_agent(&P.pass->all_done)) return;
-    const uint32_t r = ld_agent(&P.pass->round);
-    const RoundIdx R = round_idx(r);
+    // the pass state, all loads in flight together (the list counts of every buffer, selected after)
+    const uint32_t done = ld_agent(&P.pass->all_done), r = ld_agent(&P.pass->round);
+    const uint32_t any_adv = ld_agent(&P.pass->any_adv);
+    uint32_t s3[3], b3[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        s3[i] = ld_agent(&P.cnt->s[i]);
+        b3[i] = ld_agent(&P.cnt->b[i]);
+    }
+    if (done) return;
+    const uint32_t cur = r % 3u;  // this round's list (the advance below fills the next one)
+    // uniform values: scalar registers
+    const uint32_t cs = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)min(cur == 0 ? s3[0] : cur == 1 ? s3[1] : s3[2], P.cap_s));
+    const uint32_t cb = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)min(cur == 0 ? b3[0] : cur == 1 ? b3[1] : b3[2], P.cap_b));
+    const RoundIdx R = round_idx((uint32_t)__builtin_amdgcn_readfirstlane((int)r));
     const uint32_t wpb = blockDim.x / 64, w = threadIdx.x / 64;
     const uint32_t wave_gid = blockIdx.x * wpb + w, nwaves = gridDim.x * wpb;
-    if (ld_agent(&P.pass->any_adv))
-        advance_body(P, P.slot.thr, P.slot.thr_prev, P.slot.adv, r + 1, R.nxt, R.c_nxt, R.b, (int)R.b, wave_gid,
+    if (any_adv)
+        advance_body(P, P.slot.thr, P.slot.thr_prev, P.slot.adv, R.r + 1, R.nxt, R.c_nxt, R.b, (int)R.b, wave_gid,
                      nwaves, &s_wave[w]);
-    const uint32_t cs = min(ld_agent(&P.cnt->s[r % 3u]), P.cap_s), cb = min(ld_agent(&P.cnt->b[r % 3u]), P.cap_b);
     relax_round_body<NARROW>(P, R, P.slot.thr, cs, cb, &s_wave[w], wave_gid, nwaves);
 
     __syncthreads();

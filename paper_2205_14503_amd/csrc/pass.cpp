@@ -538,7 +538,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         for (;;) {
             kmark();
             for (uint32_t i = 0; i < chunk_rounds; i++) {
-                rc = hip_check(launch_round(P, Q == 1 ? o.grid_one : o.grid, o.block, st), "round");
+                rc = hip_check(launch_round(P, o.grid_tuned, o.block, st), "round");
                 relax_launches++;
                 if (rc) return rc;
             }

@@ -272,6 +272,37 @@ def test_batch_equals_single_and_oracle(stream):
                     assert single.edges == tree.edges
 
 
+def test_fixed_stride_rows(stream):
+    """Graphs whose rows have at most four entries (grids, paths, ladders)
+    run the round kernel's fixed-stride instance: no row offsets, the
+    superseded test with the row load, spilled vertices claimed at the end of
+    the unit.  Same trees as the oracle with and without the local queue, at
+    depth 1, with the light/heavy split, and in a batch; a fifth entry in one
+    row sends the same graph to the general instance."""
+    shapes = [(1, 40, 1, 3), (2, 37, 1, 2), (6, 9, 1, 1), (33, 40, 1, 3), (45, 61, 1, 1000)]
+    opts = {"default": None, "no_queue": dict(local_iters=0), "depth1": dict(local_iters=1),
+            "split": dict(delta=5, flags=st.FLAG_SPLIT), "bucketed": dict(delta=40, local_iters=2)}
+    for r, c, wlo, whi in shapes:
+        g = W.grid(r, c, wlo, whi, master=r * 100 + c)
+        for k in (1, 2, 7, 30):
+            seeds = W.sample(np.arange(g.n, dtype=np.uint32), min(k, g.n), master=k, stream=300 + r)
+            for name, opt in opts.items():
+                check_case(g, seeds, stream, opt, f"grid {r}x{c} k={k} {name}")
+    g = W.grid(40, 50, 1, 4, master=5)
+    sets = [W.sample(np.arange(g.n, dtype=np.uint32), k, master=2, stream=400 + k) for k in (2, 9, 33, 150, 1)]
+    with st.Graph(g, 0, stream) as dg:
+        say("fixed-stride rows, batch")
+        for q, (code, tree) in enumerate(dg.solve_batch(sets)):
+            ref = O.solve(g, sets[q])
+            assert code == ref.code == st.OK
+            assert tree.edges == ref.edges and tree.total == ref.total, f"query {q}"
+    # two interior vertices with five entries: the general instance, same results
+    e = [(int(a), int(b), int(w)) for a, b, w, _ in zip(*g.edges())] + [(51, g.n - 52, 3)]
+    g5 = W.from_edges(g.n, e)
+    say("grid plus one long edge")
+    check_case(g5, sets[2], stream, None, "grid + long edge")
+
+
 def test_seed_strategies(stream):
     """The paper's seed-selection variants (BFS-level, uniform, eccentric,
     proximate) give the same trees as the oracle."""
