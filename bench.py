@@ -109,6 +109,15 @@ def pmc_summary(args):
     print("\n".join(lines))
 
 
+def _trace_name(raw: str) -> str:
+    """A kernel's demangled name without return type, template arguments and
+    parameters ("void stn::k_round<true>(stn::VorParams)" -> "stn::k_round")."""
+    name = raw.split("(")[0]
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("<")[0]
+
+
 def trace_summary(args):
     """Per-kernel durations over the timed region of one bench.py run under
     rocprofv3 --kernel-trace (its JSON line gives steps and relaxation
@@ -119,11 +128,11 @@ def trace_summary(args):
     line = json.loads([x for x in open(json_file) if x.startswith("{")][-1])
     rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
     nk = int(round(line["steps"] * line["roofline"]["launches_per_step"]))
-    kr = [i for i, r in enumerate(rows) if r["Kernel_Name"].startswith("stn::k_round")]
+    kr = [i for i, r in enumerate(rows) if _trace_name(r["Kernel_Name"]) == "stn::k_round"]
     first = kr[-nk]
     acc = {}
     for r in rows[first:]:
-        name = r["Kernel_Name"].split("(")[0]
+        name = _trace_name(r["Kernel_Name"])
         acc.setdefault(name, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     total = sum(sum(v) for v in acc.values())
     print(f"Timed region: {line['steps']} steps of {line['config']['workload']}, "
