@@ -127,6 +127,9 @@ typedef struct steiner_stats {
  * caller's ids and every result is unchanged: the tie rules are evaluated on
  * the caller's ids and CSR offsets.  Cost: 8 more device bytes per entry and
  * per vertex, and host work at upload (a sort per row).
+ * Device memory held: 4 B per vertex and 8 B per entry (the CSR), and, when
+ * every row has at most 4 entries (a grid), 32 B more per vertex for a
+ * fixed-stride copy of the rows that the Voronoi pass reads instead.
  * EINVAL for n == 0, non-monotone row_ptr, row_ptr[0] != 0, row_ptr[n] != nnz,
  * nnz >= 2^32, col >= n, w == 0, unsorted rows, (STEINER_UPLOAD_SYMMETRY)
  * asymmetry, or both order flags. */
