@@ -127,3 +127,26 @@ def test_server_disconnected_query(graph):
         assert st.steiner_server_wait(srv, t).edges == O.solve(g, cand[:10]).edges
     finally:
         st.steiner_server_destroy(srv)
+
+
+def test_server_fixed_stride_rows(graph):
+    """A grid (every row at most four entries) is served by the round kernel's
+    fixed-stride instance: same trees in the mix, alone and by the oracle."""
+    import torch
+    g = W.grid(60, 70, 1, 5, master=3)
+    allv = np.arange(g.n, dtype=np.uint32)
+    ks = [2, 31, 5, 120, 9, 1, 64, 17]
+    sets = [W.sample(allv, k, master=13, stream=500 + q) for q, k in enumerate(ks)]
+    with st.Graph(g, 0, torch.cuda.current_stream()) as gg:
+        say("server: grid 60x70, 8 queries, 3 slots")
+        srv = st.steiner_server_create(gg.handle, 1 << 30, 3)
+        try:
+            tickets = [st.steiner_server_submit(srv, s) for s in sets]
+            trees = [st.steiner_server_wait(srv, t) for t in tickets]
+        finally:
+            st.steiner_server_destroy(srv)
+        for q, (s, tree) in enumerate(zip(sets, trees)):
+            ref = O.solve(g, s)
+            assert ref.code == O.OK
+            assert tree.edges == ref.edges and tree.total == ref.total, f"query {q} (k={ks[q]})"
+            assert gg.solve(s).edges == tree.edges
