@@ -155,7 +155,8 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
     // host-stepped: as many workgroups as are resident at once (the round kernel's occupancy);
     // persistent: two per CU at most, the co-residency its grid barrier needs
     // passes of the host-stepped driver use the tuned count (a latency-bound graph often runs faster on
-    // fewer workgroups, batches of its queries too); the server keeps every resident one
+    // fewer workgroups), batches at least half the resident count (their frontier is larger); the server
+    // keeps every resident one
     const bool given = r.grid != 0;
     if (!given) {
         if (r.driver == 2) {
@@ -869,14 +870,16 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
     bool best_lazy = lazy_default;
     if ((rc = measure(best_d, best_l, best_split, &t, !lazy_default))) return rc;
     if (t < best) { best = t; best_lazy = !lazy_default; }
-    // then fewer relaxation workgroups (half and three quarters of the resident count), at the chosen depth and at 8
+    // then fewer relaxation workgroups (a quarter to three quarters of the resident count), at the chosen depth
+    // and at 8
     uint32_t best_grid = 0;
     const int resident = round_max_grid(256);
     if (resident >= 8) {
         std::vector<uint32_t> ls = {best_l};
         if (best_l != 8) ls.push_back(8);
         for (uint32_t l : ls)
-            for (uint32_t gsz : {(uint32_t)resident / 2, (uint32_t)resident * 3 / 4}) {
+            for (uint32_t gsz : {(uint32_t)resident / 4, (uint32_t)resident * 3 / 8, (uint32_t)resident / 2,
+                                 (uint32_t)resident * 3 / 4}) {
                 if ((rc = measure(best_d, l, best_split, &t, best_lazy, gsz))) return rc;
                 if (t < best) { best = t; best_l = l; best_grid = gsz; }
             }

@@ -535,10 +535,12 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         // the previous pass's rounds plus the deciding round and one spare, then small growing chunks
         uint32_t chunk_rounds = std::min<uint32_t>(std::max<uint32_t>(g->last_rounds + 2, 4), 256), launched = 0;
         uint32_t next_chunk = 4;
+        // a batch's frontier is larger: at least half the resident workgroups
+        const uint32_t grid = Q == 1 ? o.grid_tuned : std::max(o.grid_tuned, o.grid / 2);
         for (;;) {
             kmark();
             for (uint32_t i = 0; i < chunk_rounds; i++) {
-                rc = hip_check(launch_round(P, o.grid_tuned, o.block, st), "round");
+                rc = hip_check(launch_round(P, grid, o.block, st), "round");
                 relax_launches++;
                 if (rc) return rc;
             }
