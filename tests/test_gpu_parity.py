@@ -235,6 +235,14 @@ def test_grid2048_full_size(stream):
             key, pred = dg.voronoi(seeds, OPTION_SETS[name])
             assert np.array_equal(key, want_key)
             assert np.array_equal(pred, ref.pred)
+        # the launch configuration the benchmark times: the tuner's choice (bucket width, depth, workgroups)
+        chosen = dg.tune(seeds)
+        say(f"grid2048 tuned: {chosen}")
+        tree = dg.solve(seeds)
+        assert tree.edges == ref.edges and tree.total == ref.total
+        key, pred = dg.voronoi(seeds)
+        assert np.array_equal(key, want_key)
+        assert np.array_equal(pred, ref.pred)
 
 
 def test_tune_keeps_results(stream):
