@@ -52,6 +52,23 @@ static bool renumbering_ok(const steiner_graph *g, const std::vector<uint64_t> &
     return true;
 }
 
+// The fixed-stride copy of a graph whose rows all have at most ELL_W entries: row i of the internal CSR, two
+// (col, w) pairs per 16 bytes, ELL_NONE past the row's end; no copy for any other graph.
+static bool ell_ok(const steiner_graph *g) {
+    if (g->max_deg > stn::ELL_W) return g->d_ell == nullptr && g->dg.ell == nullptr;
+    if (!g->d_ell || g->dg.ell != g->d_ell) return false;
+    for (uint32_t i = 0; i < g->n; i++) {
+        const uint32_t b = g->d_rp[i], d = g->d_rp[i + 1] - b;
+        const uint4 r0 = g->d_ell[2 * (size_t)i], r1 = g->d_ell[2 * (size_t)i + 1];
+        const uint32_t c[4] = {r0.x, r0.z, r1.x, r1.z}, ww[4] = {r0.y, r0.w, r1.y, r1.w};
+        for (uint32_t t = 0; t < stn::ELL_W; t++) {
+            if (t < d && (c[t] != g->d_adj[b + t].x || ww[t] != g->d_adj[b + t].y)) return false;
+            if (t >= d && c[t] != stn::ELL_NONE) return false;
+        }
+    }
+    return true;
+}
+
 #define CHECK(c)                                                            \
     do {                                                                    \
         if (!(c)) {                                                         \
@@ -73,6 +90,32 @@ int main() {
     rp[n] = col.size();
     steiner_graph *g = nullptr;
     CHECK(steiner_graph_upload(n, col.size(), rp.data(), col.data(), w.data(), 0, nullptr, 1, &g) == STEINER_OK);
+    CHECK(ell_ok(g));
+    {
+        // fixed-stride rows of a renumbered graph (built from the internal CSR), with a parallel edge and a
+        // self-loop: every row still has at most four entries
+        std::vector<std::vector<std::pair<uint32_t, uint32_t>>> rows(n);  // (col, w)
+        auto edge = [&](uint32_t a, uint32_t b, uint32_t wt) {
+            rows[a].push_back({b, wt});
+            rows[b].push_back({a, wt});  // a self-loop gets both entries in its own row
+        };
+        for (uint32_t v = 0; v + 1 < n; v++) edge(v, v + 1, 2);
+        edge(20, 21, 1);
+        edge(9, 9, 4);
+        std::vector<uint64_t> rp3(n + 1);
+        std::vector<uint32_t> col3, w3;
+        for (uint32_t v = 0; v < n; v++) {
+            std::sort(rows[v].begin(), rows[v].end());
+            rp3[v] = col3.size();
+            for (auto &e : rows[v]) { col3.push_back(e.first); w3.push_back(e.second); }
+        }
+        rp3[n] = col3.size();
+        steiner_graph *g3 = nullptr;
+        CHECK(steiner_graph_upload(n, col3.size(), rp3.data(), col3.data(), w3.data(), 0, nullptr,
+                                   STEINER_UPLOAD_REORDER | 1u, &g3) == STEINER_OK);
+        CHECK(g3->reordered && g3->max_deg <= stn::ELL_W && ell_ok(g3));
+        CHECK(steiner_graph_free(g3) == STEINER_OK);
+    }
     std::vector<uint32_t> badw = w;
     badw[3] = 0;
     steiner_graph *bad = nullptr;
@@ -113,6 +156,7 @@ int main() {
             CHECK(steiner_graph_upload(n2, col2.size(), rp2.data(), col2.data(), w2.data(), 0, nullptr, fl | 1u, &g2) ==
                   STEINER_OK);
             CHECK(renumbering_ok(g2, rp2, col2, w2));
+            CHECK(ell_ok(g2));  // a hub: no fixed-stride copy
             const uint32_t seeds2[] = {4095, 17, 900, 17};
             steiner_result *r2 = nullptr;
             CHECK(steiner_solve(g2, seeds2, 4, nullptr, &r2) == STEINER_OK);
