@@ -183,19 +183,36 @@ int steiner_voronoi(steiner_graph *g, const uint32_t *seeds, uint32_t k, const s
 int steiner_boundary(steiner_graph *g, const uint32_t *seeds, uint32_t k, const steiner_options *opt,
                      uint64_t *npairs, uint32_t *pi, uint32_t *pj, uint64_t *packed, uint64_t cap);
 
-/* Serving: a request loop over a resident graph.  Requests are admitted while
- * their per-query device memory fits mem_budget_bytes and a slot is free, are
- * spliced into the running multi-query pass between relaxation rounds, and
- * their tails run as soon as their own cells converge. */
+/* Serving: a request loop over a resident graph.  Requests are admitted
+ * first come first served while a slot is free and their pool region fits
+ * the free pool, are spliced into the running multi-query pass between
+ * relaxation rounds, and their tails run as soon as their own cells converge.
+ * Everything the server allocates on the device fits mem_budget_bytes (see
+ * steiner_server_memory); EINVAL if the budget cannot hold one slot and one
+ * smallest request. */
 int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes, uint32_t max_slots,
                           const steiner_options *opt, steiner_server **out);
 int steiner_server_submit(steiner_server *s, const uint32_t *seeds, uint32_t k, uint64_t *ticket);
-/* timeout_us < 0 waits forever.  ETIMEDOUT leaves the request pending. */
+/* timeout_us < 0 waits forever.  ETIMEDOUT leaves the request pending (wait
+ * again later).  ECANCELED if the server is destroyed first.  Each ticket is
+ * consumed by the wait that returns its result or its error. */
 int steiner_server_wait(steiner_server *s, uint64_t ticket, int64_t timeout_us, steiner_result **out);
-/* Bytes a request with k seeds needs on the device (the admission charge). */
+/* Device memory of a request with k seeds: its slot's share (vertex state and
+ * frontier lists) plus its pool region (pair table, G'1 indices, MST scratch,
+ * seeds).  Submit refuses (ENOMEM) a request whose pool region exceeds the
+ * whole pool. */
 uint64_t steiner_server_query_bytes(const steiner_server *s, uint32_t k);
-/* Stops the server; requests not yet finished are canceled.  No other call on
- * this server may be in progress or follow. */
+/* How the budget is split (any pointer may be NULL): fixed_bytes (control
+ * region, tree output, vertex marks) + slots * slot_bytes + pool_bytes equals
+ * mem_budget_bytes, and is everything the server holds on the device.  slots
+ * is max_slots, or fewer if the budget cannot hold that many slots and one
+ * smallest request each. */
+int steiner_server_memory(const steiner_server *s, uint64_t *fixed_bytes, uint64_t *slot_bytes, uint32_t *slots,
+                          uint64_t *pool_bytes);
+/* Stops the server; requests not yet finished are canceled.  A thread blocked
+ * in steiner_server_wait at that moment returns STEINER_ECANCELED, and destroy
+ * returns after it has left.  No call on this server may start once destroy
+ * has begun. */
 int steiner_server_destroy(steiner_server *s);
 
 const char *steiner_strerror(int code);

@@ -42,7 +42,8 @@ EXPORTS = [
     "steiner_graph_upload", "steiner_graph_upload_device", "steiner_graph_free", "steiner_graph_tune", "steiner_solve",
     "steiner_solve_batch", "steiner_result_edges", "steiner_result_total", "steiner_result_stats",
     "steiner_result_free", "steiner_voronoi", "steiner_boundary", "steiner_server_create",
-    "steiner_server_submit", "steiner_server_wait", "steiner_server_query_bytes", "steiner_server_destroy",
+    "steiner_server_submit", "steiner_server_wait", "steiner_server_query_bytes", "steiner_server_memory",
+    "steiner_server_destroy",
     "steiner_strerror", "steiner_last_error",
 ]
 
@@ -97,6 +98,7 @@ def load(path: str | None = None):
         "steiner_server_submit": (i32, [vp, vp, u32, vp]),
         "steiner_server_wait": (i32, [vp, u64, i64, vp]),
         "steiner_server_query_bytes": (u64, [vp, u32]),
+        "steiner_server_memory": (i32, [vp, vp, vp, vp, vp]),
         "steiner_server_destroy": (i32, [vp]),
         "steiner_strerror": (ctypes.c_char_p, [i32]),
         "steiner_last_error": (ctypes.c_char_p, []),
@@ -295,6 +297,14 @@ def steiner_server_wait(s: int, ticket: int, timeout_us: int = -1) -> Tree:
 
 def steiner_server_query_bytes(s: int, k: int) -> int:
     return int(load().steiner_server_query_bytes(s, k))
+
+
+def steiner_server_memory(s: int) -> dict:
+    """How the server's budget is split: fixed + slots * slot_bytes + pool = budget."""
+    f, sb, p = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    n = ctypes.c_uint32()
+    _check(load().steiner_server_memory(s, ctypes.byref(f), ctypes.byref(sb), ctypes.byref(n), ctypes.byref(p)))
+    return {"fixed_bytes": f.value, "slot_bytes": sb.value, "slots": n.value, "pool_bytes": p.value}
 
 
 def steiner_server_destroy(s: int) -> None:

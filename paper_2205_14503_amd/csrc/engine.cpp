@@ -38,21 +38,36 @@ int fail(int code, const char *fmt, ...) {
 }
 
 // Allocation fault injection for error-path tests: STEINER_FAULT_ALLOC_AFTER=N
-// makes the (N+1)-th device allocation of the process fail.
-static long g_alloc_calls = 0;
-static long fault_alloc_after() {
-    static long v = -2;
-    if (v == -2) {
+// (read at the first allocation) or set_fault_alloc_after(N) makes every
+// device or pinned-host allocation after the first N of the process fail.
+static std::atomic<long> g_alloc_calls{0};
+static std::atomic<long> g_fault_after{-2};  // -2: not yet read from the environment, -1: off
+static bool fault_injected(size_t bytes) {
+    long lim = g_fault_after.load(std::memory_order_relaxed);
+    if (lim == -2) {
         const char *s = getenv("STEINER_FAULT_ALLOC_AFTER");
-        v = s ? atol(s) : -1;
+        long want = s ? atol(s) : -1;
+        g_fault_after.compare_exchange_strong(lim, want);
+        lim = g_fault_after.load(std::memory_order_relaxed);
     }
-    return v;
+    const long c = g_alloc_calls.fetch_add(1, std::memory_order_relaxed);
+    if (lim >= 0 && c >= lim) {
+        fail(STEINER_ENOMEM, "injected allocation failure (%zu bytes)", bytes);
+        return true;
+    }
+    return false;
 }
 
+void set_fault_alloc_after(long n) {
+    g_alloc_calls.store(0);
+    g_fault_after.store(n < 0 ? -1 : n);
+}
+
+long alloc_calls() { return g_alloc_calls.load(); }
+
 int dev_alloc(void **p, size_t bytes) {
-    long lim = fault_alloc_after();
-    long c = __atomic_fetch_add(&g_alloc_calls, 1, __ATOMIC_RELAXED);
-    if (lim >= 0 && c >= lim) return fail(STEINER_ENOMEM, "injected allocation failure (%zu bytes)", bytes);
+    *p = nullptr;
+    if (fault_injected(bytes)) return STEINER_ENOMEM;
     if (bytes == 0) bytes = 8;
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
@@ -81,10 +96,10 @@ void DevBuf::release() {
     bytes = 0;
 }
 
-int DevBuf::ensure(size_t want) {
+int DevBuf::ensure(size_t want, bool exact) {
     if (want <= bytes && ptr) return STEINER_OK;
     release();
-    size_t cap = want + want / 8 + 256;
+    size_t cap = exact ? want : want + want / 8 + 256;
     int rc = dev_alloc(&ptr, cap);
     if (rc) return rc;
     bytes = cap;
@@ -101,6 +116,7 @@ int HostPinned::ensure(size_t want) {
     if (want <= bytes && ptr) return STEINER_OK;
     release();
     size_t cap = want + want / 8 + 256;
+    if (fault_injected(cap)) return STEINER_ENOMEM;
     if (hipHostMalloc(&ptr, cap, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         ptr = nullptr;

@@ -13,6 +13,10 @@ namespace stn {
 
 int fail(int code, const char *fmt, ...);
 int dev_alloc(void **p, size_t bytes);
+// Error-path testing: every device or pinned-host allocation after the next n
+// fails with STEINER_ENOMEM (n < 0: off); resets the allocation count.
+void set_fault_alloc_after(long n);
+long alloc_calls();
 void dev_free(void *p);
 int hip_check(hipError_t e, const char *what);
 
@@ -20,7 +24,7 @@ int hip_check(hipError_t e, const char *what);
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
-    int ensure(size_t want);
+    int ensure(size_t want, bool exact = false);  // exact: no growth headroom
     void release();
     template <typename T>
     T *as() const { return (T *)ptr; }
@@ -51,7 +55,8 @@ struct TailScratch {
     HostPinned host;
     uint32_t mark_n = 0;  // mark holds this many zero bytes
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    int prepare(uint32_t n, uint32_t k, uint64_t m, hipStream_t st);
+    // own_mst: the MST scratch lives in `mst` (else the caller passes a region of mst_scratch_bytes)
+    int prepare(uint32_t n, uint32_t k, uint64_t m, bool own_mst, hipStream_t st);
     void release();
 };
 
@@ -200,9 +205,14 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs);
 // indices g1_idx into its pair table pt), the kept cross-cell edges, the pred
 // walks and D.  key / pred are the query's slot arrays.  The tree's edges come
 // back sorted by (a, b, w); EDISCONNECTED if the MST has fewer than k-1 edges.
+// mst_buf: a device region of mst_scratch_bytes(k, m) for the MST, or null
+// for ts.mst.
 int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
                  const uint64_t *pt, const uint32_t *tr, const uint32_t *g1_idx, uint32_t m, bool pred_ready,
-                 TailScratch &ts, std::unique_ptr<steiner_result> &out, double *ms_mst, double *ms_expand);
+                 TailScratch &ts, uint8_t *mst_buf, std::unique_ptr<steiner_result> &out, double *ms_mst,
+                 double *ms_expand);
+// Bytes of the MST's scratch for k seeds and a G'1 of m entries.
+size_t mst_scratch_bytes(uint32_t k, uint64_t m);
 // Pair-table ranks of a query's seeds (see pair_slot): rk[i] is the rank of
 // seed index i among the seeds ordered by internal id and rk[k + r] the seed
 // index of rank r.  Empty when the graph keeps the caller's order (identity).

@@ -23,7 +23,7 @@ struct CompactParams {
     const uint32_t *const *ts;  // per-slot seed index of each table rank (null: identity)
     const uint64_t *pt_len;     // per-slot pair-table lengths
     uint32_t *const *out_idx;   // per-slot pair index output
-    uint64_t *const *out_val;   // per-slot packed value output
+    uint64_t *const *out_val;   // per-slot packed value output (a null entry: indices only)
     const uint64_t *out_cap;    // per-slot capacities
     uint32_t *out_cnt;          // per-slot counts; the output indices are in seed-index order (i < j: j(j-1)/2 + i)
     const uint32_t *slot_ids;

@@ -1409,6 +1409,7 @@ __global__ void __launch_bounds__(256) k_compact(CompactParams C) {
         const uint32_t slot = C.slot_ids[si];
         const uint64_t *pt = C.pt[slot];
         const uint32_t *ts = C.ts ? C.ts[slot] : nullptr;
+        uint64_t *ov = C.out_val[slot];
         const uint64_t len = C.pt_len[slot];
         const uint64_t tiles = (len + 1023) / 1024;
         for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {  // uniform per workgroup
@@ -1444,7 +1445,7 @@ __global__ void __launch_bounds__(256) k_compact(CompactParams C) {
                             q = (uint32_t)pair_index(min(x, y), max(x, y));
                         }
                         C.out_idx[slot][pos] = q;
-                        C.out_val[slot][pos] = val[j];
+                        if (ov) ov[pos] = val[j];
                     } else {
                         atomicOr(&C.pass->err, ERR_LIST_OVERFLOW);
                     }

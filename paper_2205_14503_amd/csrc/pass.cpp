@@ -163,10 +163,14 @@ int ClusterSet::build(steiner_graph *g) {
     return STEINER_OK;
 }
 
-int TailScratch::prepare(uint32_t n, uint32_t k, uint64_t m, hipStream_t st) {
-    int rc;
+size_t mst_scratch_bytes(uint32_t k, uint64_t m) {
     const size_t k4 = ((size_t)k * 4 + 255) & ~(size_t)255, m4 = ((size_t)m * 4 + 255) & ~(size_t)255;
-    if ((rc = mst.ensure(256 + 3 * k4 + 2 * k4 + 2 * m4))) return rc;
+    return 256 + 5 * k4 + 2 * m4;
+}
+
+int TailScratch::prepare(uint32_t n, uint32_t k, uint64_t m, bool own_mst, hipStream_t st) {
+    int rc;
+    if (own_mst && (rc = mst.ensure(mst_scratch_bytes(k, m)))) return rc;
     if ((rc = out.ensure((size_t)n * 12 + 16))) return rc;
     if ((rc = host.ensure(64))) return rc;
     const size_t mark_bytes = ((size_t)n + 3) / 4 * 4;
@@ -195,12 +199,13 @@ void TailScratch::release() {
 
 int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
                  const uint64_t *pt, const uint32_t *tr, const uint32_t *g1_idx, uint32_t m, bool pred_ready,
-                 TailScratch &ts, std::unique_ptr<steiner_result> &out, double *ms_mst, double *ms_expand) {
+                 TailScratch &ts, uint8_t *mst_buf, std::unique_ptr<steiner_result> &out, double *ms_mst,
+                 double *ms_expand) {
     const uint32_t n = g->n;
     int rc;
-    if ((rc = ts.prepare(n, k, m, st))) return rc;
+    if ((rc = ts.prepare(n, k, m, mst_buf == nullptr, st))) return rc;
     const size_t k4 = ((size_t)k * 4 + 255) & ~(size_t)255, m4 = ((size_t)m * 4 + 255) & ~(size_t)255;
-    uint8_t *base = ts.mst.as<uint8_t>();
+    uint8_t *base = mst_buf ? mst_buf : ts.mst.as<uint8_t>();
     MstParams M{};
     M.pt = pt;
     M.tr = tr;
@@ -667,7 +672,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         }
         int trc = tree_from_g1(g, st, P.key + (size_t)s * n, P.aux + (size_t)s * n, k, ws.pt.as<uint64_t>() + pt_off[s],
                                ranked ? d_tr + sd_off[s] : nullptr,
-                               ws.cidx.as<uint32_t>() + oc_off[s], m, SP.with_pred != 0, ws.tail, qq.result,
+                               ws.cidx.as<uint32_t>() + oc_off[s], m, SP.with_pred != 0, ws.tail, nullptr, qq.result,
                                o.timing ? &ms_mst : nullptr, o.timing ? &ms_expand : nullptr);
         if (trc == STEINER_EDISCONNECTED) {
             qq.status = trc;

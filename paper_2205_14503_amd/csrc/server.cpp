@@ -101,7 +101,9 @@ __global__ void k_iota(uint32_t *p, uint32_t n) {
 struct steiner_server {
     steiner_graph *g = nullptr;
     Options o{};
-    uint64_t budget = 0, used = 0, slot_bytes = 0;
+    // Device memory: fixed_bytes (control region, tail output and marks, list headroom) + S * slot_bytes
+    // (per-slot vertex state and frontier lists) + the pool (per-request regions) = budget.
+    uint64_t budget = 0, fixed_bytes = 0, slot_bytes = 0, pool_bytes = 0, used = 0;
     uint32_t S = 0;  // slots
     hipStream_t s_main = nullptr, s_tail = nullptr;
     DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, pool;
@@ -120,27 +122,41 @@ struct steiner_server {
     std::vector<int> slot_state;
     std::deque<int> tail_q;
     uint64_t next_ticket = 1;
+    uint32_t waiters = 0;  // threads inside steiner_server_wait (destroy waits for them to leave)
     bool stopping = false;
     int fatal = STEINER_OK;
     std::thread sched, tailer;
 
-    uint64_t pool_need(uint32_t k) const {
-        const uint64_t P_ = (uint64_t)k * (k - 1) / 2;
-        const uint64_t oc = std::min<uint64_t>(P_, half);
-        return ((8 * P_ + 255) & ~255ull) + ((4 * oc + 255) & ~255ull) + ((8 * oc + 255) & ~255ull) +
-               ((12ull * k + 255) & ~255ull);
-    }
-    // A request's pool region: pair table, G'1 indices, G'1 values, then its seeds, their table ranks and the
+    // A request's pool region: pair table (8 B per pair), G'1 pair indices (4 B per entry, at most one per
+    // pair and one per edge), the MST's scratch over that G'1, then its seeds, their table ranks and the
     // inverse ranks (k entries each).
-    uint32_t *seeds_of(const Request *r) const {
-        const uint64_t k = r->S.size(), P_ = k * (k - 1) / 2, oc = std::min<uint64_t>(P_, half);
-        return (uint32_t *)(pool.as<uint8_t>() + r->pool_off + ((8 * P_ + 255) & ~255ull) + ((4 * oc + 255) & ~255ull) +
-                            ((8 * oc + 255) & ~255ull));
+    static uint64_t al(uint64_t b) { return (b + 255) & ~255ull; }
+    uint64_t g1_cap(uint32_t k) const { return std::min<uint64_t>((uint64_t)k * (k - 1) / 2, half); }
+    uint64_t pool_need(uint32_t k) const {
+        const uint64_t P_ = (uint64_t)k * (k - 1) / 2, oc = g1_cap(k);
+        return al(8 * P_) + al(4 * oc) + al(mst_scratch_bytes(k, oc)) + al(12ull * k);
     }
+    uint8_t *region(const Request *r, int part) const {  // 0 pair table, 1 G'1 indices, 2 MST, 3 seeds
+        const uint64_t k = r->S.size(), P_ = k * (k - 1) / 2, oc = g1_cap((uint32_t)k);
+        const uint64_t off[4] = {0, al(8 * P_), al(8 * P_) + al(4 * oc),
+                                 al(8 * P_) + al(4 * oc) + al(mst_scratch_bytes((uint32_t)k, oc))};
+        return pool.as<uint8_t>() + r->pool_off + off[part];
+    }
+    uint32_t *seeds_of(const Request *r) const { return (uint32_t *)region(r, 3); }
 
     void run_sched();
     void run_tail();
     int admit(Request *r, int slot);
+    void free_device() {
+        DevBuf *bufs[] = {&key, &aux, &dirty, &settled, &items_s[0], &items_s[1], &items_b[0], &items_b[1], &ctl,
+                          &heavy_pe, &pool};
+        for (DevBuf *b : bufs) b->release();
+        hbuf.release();
+        tail.release();
+        if (s_main) (void)hipStreamDestroy(s_main);
+        if (s_tail) (void)hipStreamDestroy(s_tail);
+        s_main = s_tail = nullptr;
+    }
 };
 
 // ---------------------------------------------------------------- helpers
@@ -152,11 +168,9 @@ static double ms_since(std::chrono::steady_clock::time_point t) {
 int steiner_server::admit(Request *r, int slot) {
     const uint32_t k = (uint32_t)r->S.size();
     const uint64_t P_ = (uint64_t)k * (k - 1) / 2;
-    const uint64_t oc = std::min<uint64_t>(P_, half);
-    uint8_t *base = pool.as<uint8_t>() + r->pool_off;
-    uint64_t *pt = (uint64_t *)base;
-    uint32_t *oi = (uint32_t *)(base + ((8 * P_ + 255) & ~255ull));
-    uint64_t *ov = (uint64_t *)((uint8_t *)oi + ((4 * oc + 255) & ~255ull));
+    const uint64_t oc = g1_cap(k);
+    uint64_t *pt = (uint64_t *)region(r, 0);
+    uint32_t *oi = (uint32_t *)region(r, 1);
     uint32_t *seeds = seeds_of(r);
     uint8_t *c = ctl.as<uint8_t>();
     int rc = hip_check(hipMemcpyAsync(seeds, r->S.data(), 4ull * k, hipMemcpyHostToDevice, s_main), "H2D seeds");
@@ -168,7 +182,7 @@ int steiner_server::admit(Request *r, int slot) {
                        (uint64_t *)(c + L.pt_len), (uint64_t *)(c + L.oidx_ptr), (uint64_t *)(c + L.oval_ptr),
                        (uint64_t *)(c + L.ocap), (uint64_t *)(c + L.tr_ptr), (uint64_t *)(c + L.ts_ptr),
                        (uint32_t *)(c + L.slot_err), (uint32_t *)(c + L.out_cnt), (uint32_t)slot,
-                       (uint64_t)(uintptr_t)pt, P_, (uint64_t)(uintptr_t)oi, (uint64_t)(uintptr_t)ov, oc,
+                       (uint64_t)(uintptr_t)pt, P_, (uint64_t)(uintptr_t)oi, 0ull, oc,
                        ranked ? (uint64_t)(uintptr_t)(seeds + k) : 0ull, ranked ? (uint64_t)(uintptr_t)(seeds + 2 * k) : 0ull);
     if ((rc = hip_check(hipGetLastError(), "slot tables"))) return rc;
     if ((rc = hip_check(launch_fill_u64(pt, P_, KEY_INF, s_main), "pair table"))) return rc;
@@ -193,13 +207,13 @@ void steiner_server::run_sched() {
             for (uint32_t s = 0; s < S; s++)
                 if (slot_state[s] == SLOT_FREE) { slot = (int)s; break; }
             if (slot < 0) break;
-            const uint64_t need = slot_bytes + pool_need((uint32_t)r->S.size());
-            if (used + need > budget) break;
+            const uint64_t need = pool_need((uint32_t)r->S.size());
+            if (used + need > pool_bytes) break;
             uint64_t off = 0;
-            if (!pa.alloc(pool_need((uint32_t)r->S.size()), &off)) break;
+            if (!pa.alloc(need, &off)) break;
             pending.pop_front();
             r->pool_off = off;
-            r->pool_bytes = pool_need((uint32_t)r->S.size());
+            r->pool_bytes = need;
             r->charge = need;
             r->slot = slot;
             used += need;
@@ -312,13 +326,15 @@ void steiner_server::run_tail() {
                 status = fail(STEINER_EOVERFLOW, "distance or cross-cell sum does not fit in 32 bits");
             } else {
                 const uint32_t k = (uint32_t)r->S.size();
-                const uint64_t P_ = r->pt_len;
-                uint8_t *base = pool.as<uint8_t>() + r->pool_off;
-                const uint32_t *oi = (const uint32_t *)(base + ((8 * P_ + 255) & ~255ull));
+                const uint32_t *oi = (const uint32_t *)region(r, 1);
                 const uint32_t *tr = r->rk.empty() ? nullptr : seeds_of(r) + k;
-                status = tree_from_g1(g, s_tail, P.key + (size_t)slot * n, P.aux + (size_t)slot * n, k,
-                                      (const uint64_t *)base, tr, oi, cnt, SP.with_pred != 0, tail, res, nullptr,
-                                      nullptr);
+                if (cnt > r->oc_cap) {
+                    status = fail(STEINER_EDEVICE, "G'1 overflow (%u entries)", cnt);
+                } else {
+                    status = tree_from_g1(g, s_tail, P.key + (size_t)slot * n, P.aux + (size_t)slot * n, k,
+                                          (const uint64_t *)region(r, 0), tr, oi, cnt, SP.with_pred != 0, tail,
+                                          region(r, 2), res, nullptr, nullptr);
+                }
                 if (!status) res->stats.pairs = cnt;
             }
         }
@@ -345,6 +361,16 @@ extern "C" uint64_t steiner_server_query_bytes(const steiner_server *s, uint32_t
     return s->slot_bytes + s->pool_need(std::max<uint32_t>(k, 2));
 }
 
+extern "C" int steiner_server_memory(const steiner_server *s, uint64_t *fixed_bytes, uint64_t *slot_bytes,
+                                     uint32_t *slots, uint64_t *pool_bytes) {
+    if (!s) return fail(STEINER_EINVAL, "NULL server");
+    if (fixed_bytes) *fixed_bytes = s->fixed_bytes;
+    if (slot_bytes) *slot_bytes = s->slot_bytes;
+    if (slots) *slots = s->S;
+    if (pool_bytes) *pool_bytes = s->pool_bytes;
+    return STEINER_OK;
+}
+
 extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes, uint32_t max_slots,
                                      const steiner_options *opt, steiner_server **out) {
     if (!g || !out) return fail(STEINER_EINVAL, "NULL argument");
@@ -352,33 +378,48 @@ extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes
     int rc = hip_check(hipSetDevice(g->device), "hipSetDevice");
     if (rc) return rc;
     std::unique_ptr<steiner_server> s(new steiner_server());
+    struct Cleanup {  // device memory and streams of a server that failed to start
+        std::unique_ptr<steiner_server> &s;
+        ~Cleanup() {
+            if (s) s->free_device();
+        }
+    } cleanup{s};
     s->g = g;
     s->o = resolve_options(g, opt);
     s->o.driver = 1;
     s->o.timing = false;
     s->o.counting = false;
     const uint32_t n = g->n;
-    s->slot_bytes = 14ull * n + 4ull * g->nheavy;
+    const uint64_t chunks = big_row_chunks(g, s->o.small_max, s->o.chunk);
+    // per slot: key 8 + stamp/pred 4 + park 1 + settled 1 bytes per vertex, the heavy rows' pred minima, and the
+    // slot's share of the two S lists (two entries of 8 bytes per vertex each) and of the two B lists
+    s->slot_bytes = 14ull * n + 4ull * g->nheavy + 32ull * n + 32ull * chunks;
     s->half = g->nnz / 2 + 1;
+    const uint64_t mark_bytes = ((uint64_t)n + 3) / 4 * 4, out_bytes = 12ull * n + 16;
+    s->fixed_bytes = steiner_server::al(Layout(max_slots).total) + steiner_server::al(mark_bytes) +
+                     steiner_server::al(out_bytes) + 4 * steiner_server::al(64 * 8) + 4;
     s->budget = mem_budget_bytes;
-    if (s->budget < s->slot_bytes + s->pool_need(2))
-        return fail(STEINER_EINVAL, "memory budget below one query's state (%llu bytes)",
-                    (unsigned long long)(s->slot_bytes + s->pool_need(2)));
-    s->S = (uint32_t)std::min<uint64_t>(max_slots, s->budget / s->slot_bytes);
+    const uint64_t one = s->fixed_bytes + s->slot_bytes + s->pool_need(2);
+    if (s->budget < one)
+        return fail(STEINER_EINVAL, "memory budget below one query's state (%llu bytes)", (unsigned long long)one);
+    s->S = (uint32_t)std::min<uint64_t>(max_slots, (s->budget - s->fixed_bytes) / (s->slot_bytes + s->pool_need(2)));
     const uint32_t S = s->S;
+    s->pool_bytes = s->budget - s->fixed_bytes - (uint64_t)S * s->slot_bytes;
     const uint64_t cap_s = 2ull * S * n + 64;
-    const uint64_t cap_b = 2ull * S * big_row_chunks(g, s->o.small_max, s->o.chunk) + 64;
+    const uint64_t cap_b = 2ull * S * chunks + 64;
     if (cap_s >= (1ull << 32) || cap_b >= (1ull << 32)) return fail(STEINER_ENOMEM, "too many slots for this graph");
     s->L = Layout(S);
     const size_t SN = (size_t)S * n;
-    if ((rc = s->key.ensure(SN * 8)) || (rc = s->aux.ensure(SN * 4)) || (rc = s->dirty.ensure(SN)) ||
-        (rc = s->settled.ensure(SN)) ||
-        (rc = s->items_s[0].ensure(cap_s * 8)) || (rc = s->items_s[1].ensure(cap_s * 8)) ||
-        (rc = s->items_b[0].ensure(cap_b * 8)) || (rc = s->items_b[1].ensure(cap_b * 8)) ||
-        (rc = s->ctl.ensure(s->L.total)) || (rc = s->heavy_pe.ensure((size_t)S * g->nheavy * 4 + 4)) ||
-        (rc = s->pool.ensure(s->budget)) || (rc = s->hbuf.ensure(s->L.total + 4096)))
+    // exact sizes: everything the server holds on the device stays within the budget
+    if ((rc = s->key.ensure(SN * 8, true)) || (rc = s->aux.ensure(SN * 4, true)) || (rc = s->dirty.ensure(SN, true)) ||
+        (rc = s->settled.ensure(SN, true)) ||
+        (rc = s->items_s[0].ensure(cap_s * 8, true)) || (rc = s->items_s[1].ensure(cap_s * 8, true)) ||
+        (rc = s->items_b[0].ensure(cap_b * 8, true)) || (rc = s->items_b[1].ensure(cap_b * 8, true)) ||
+        (rc = s->ctl.ensure(s->L.total, true)) || (rc = s->heavy_pe.ensure((size_t)S * g->nheavy * 4 + 4, true)) ||
+        (rc = s->tail.mark.ensure(mark_bytes, true)) || (rc = s->tail.out.ensure(out_bytes, true)) ||
+        (rc = s->pool.ensure(s->pool_bytes, true)) || (rc = s->hbuf.ensure(s->L.total + 4096)))
         return rc;
-    s->pa.init(s->budget);
+    s->pa.init(s->pool_bytes);
     if ((rc = hip_check(hipStreamCreateWithFlags(&s->s_main, hipStreamNonBlocking), "stream"))) return rc;
     if ((rc = hip_check(hipStreamCreateWithFlags(&s->s_tail, hipStreamNonBlocking), "stream"))) return rc;
     VorParams &P = s->P;
@@ -393,6 +434,9 @@ extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes
     P.items_b[1] = s->items_b[1].as<uint64_t>();
     bind_state(P, s->o, cap_s, cap_b);
     if ((rc = hip_check(launch_pass_reset(P, s->s_main), "pass reset"))) return rc;
+    if ((rc = hip_check(launch_fill_u32(s->tail.mark.as<uint32_t>(), mark_bytes / 4, 0u, s->s_main), "mark clear")))
+        return rc;
+    s->tail.mark_n = n;
     hipLaunchKernelGGL(k_iota, dim3((S + 255) / 256), dim3(256), 0, s->s_main,
                        (uint32_t *)(s->ctl.as<uint8_t>() + s->L.slot_ids), S);
     if ((rc = hip_check(hipStreamSynchronize(s->s_main), "server init"))) return rc;
@@ -418,7 +462,7 @@ extern "C" int steiner_server_submit(steiner_server *s, const uint32_t *seeds, u
     if (r->S.size() < 2) {  // k == 1: empty tree, D = 0
         r->result.reset(new steiner_result());
         r->done = true;
-    } else if (s->slot_bytes + s->pool_need((uint32_t)r->S.size()) > s->budget) {
+    } else if (s->pool_need((uint32_t)r->S.size()) > s->pool_bytes) {
         return fail(STEINER_ENOMEM, "a query with %zu seeds needs more than the server's memory budget", r->S.size());
     } else {
         s->pending.push_back(r.get());
@@ -437,14 +481,28 @@ extern "C" int steiner_server_wait(steiner_server *s, uint64_t ticket, int64_t t
     if (it == s->reqs.end()) return fail(STEINER_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
     Request *r = it->second;
     auto ready = [&] { return r->done; };
+    s->waiters++;
+    bool in_time = true;
     if (timeout_us < 0) {
         s->cv_done.wait(lk, ready);
-    } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
-        return fail(STEINER_ETIMEDOUT, "request %llu still running", (unsigned long long)ticket);
+    } else {
+        // the deadline is on the steady clock; each sleep is bounded through the system clock, whose
+        // timed wait every threading tool understands
+        const auto deadline = std::chrono::steady_clock::now() + std::chrono::microseconds(timeout_us);
+        for (;;) {
+            if (ready()) break;
+            const auto now = std::chrono::steady_clock::now();
+            if (now >= deadline) break;
+            s->cv_done.wait_until(lk, std::chrono::system_clock::now() + (deadline - now));
+        }
+        in_time = ready();
     }
+    s->waiters--;
+    if (s->stopping) s->cv_done.notify_all();  // destroy waits for the waiters to leave
+    if (!in_time) return fail(STEINER_ETIMEDOUT, "request %llu still running", (unsigned long long)ticket);
     const int status = r->status;
     std::unique_ptr<steiner_result> res = std::move(r->result);
-    s->reqs.erase(it);
+    s->reqs.erase(r->ticket);
     delete r;
     if (status) return fail(status, "request failed: %s", steiner_strerror(status));
     if (!res) return fail(STEINER_EDEVICE, "missing result");
@@ -463,26 +521,22 @@ extern "C" int steiner_server_destroy(steiner_server *s) {
     if (s->sched.joinable()) s->sched.join();
     if (s->tailer.joinable()) s->tailer.join();
     {
-        std::lock_guard<std::mutex> lk(s->mu);
+        std::unique_lock<std::mutex> lk(s->mu);
         for (auto &kv : s->reqs)
             if (!kv.second->done) {
                 kv.second->status = STEINER_ECANCELED;
                 kv.second->done = true;
             }
         s->cv_done.notify_all();
+        // threads blocked in steiner_server_wait take their (canceled) results and leave first
+        s->cv_done.wait(lk, [&] { return s->waiters == 0; });
     }
     (void)hipSetDevice(s->g->device);
     (void)hipStreamSynchronize(s->s_main);
     (void)hipStreamSynchronize(s->s_tail);
     for (auto &kv : s->reqs) delete kv.second;
     s->reqs.clear();
-    DevBuf *bufs[] = {&s->key, &s->aux, &s->dirty, &s->settled, &s->items_s[0], &s->items_s[1], &s->items_b[0], &s->items_b[1],
-                      &s->ctl, &s->heavy_pe, &s->pool};
-    for (DevBuf *b : bufs) b->release();
-    s->hbuf.release();
-    s->tail.release();
-    if (s->s_main) (void)hipStreamDestroy(s->s_main);
-    if (s->s_tail) (void)hipStreamDestroy(s->s_tail);
+    s->free_device();
     delete s;
     return STEINER_OK;
 }

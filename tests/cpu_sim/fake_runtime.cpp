@@ -6,8 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <vector>
 #include <thread>
+#include <unordered_map>
+#include <vector>
 
 #include "kernels.h"
 
@@ -17,6 +18,10 @@ std::mutex launch_mu;
 }
 
 static std::atomic<long> g_live_allocs{0};
+static std::mutex g_alloc_mu;
+static std::unordered_map<void *, size_t> g_dev_sizes;  // live device allocations (not pinned host ones)
+static long g_live_dev_bytes = 0;
+static std::atomic<bool> g_stall{false};
 
 hipError_t hipSetDevice(int) { return hipSuccess; }
 hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
@@ -25,14 +30,36 @@ hipError_t hipMalloc(void **p, size_t n) {
     *p = calloc(1, n ? n : 1);
     if (!*p) return hipErrorOutOfMemory;
     g_live_allocs++;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_dev_sizes[*p] = n;
+    g_live_dev_bytes += (long)n;
     return hipSuccess;
 }
 hipError_t hipFree(void *p) {
+    if (p) {
+        {
+            std::lock_guard<std::mutex> lk(g_alloc_mu);
+            auto it = g_dev_sizes.find(p);
+            if (it != g_dev_sizes.end()) {
+                g_live_dev_bytes -= (long)it->second;
+                g_dev_sizes.erase(it);
+            }
+        }
+        free(p);
+        g_live_allocs--;
+    }
+    return hipSuccess;
+}
+hipError_t hipHostMalloc(void **p, size_t n, unsigned) {
+    *p = calloc(1, n ? n : 1);
+    if (!*p) return hipErrorOutOfMemory;
+    g_live_allocs++;
+    return hipSuccess;
+}
+hipError_t hipHostFree(void *p) {
     if (p) { free(p); g_live_allocs--; }
     return hipSuccess;
 }
-hipError_t hipHostMalloc(void **p, size_t n, unsigned) { return hipMalloc(p, n); }
-hipError_t hipHostFree(void *p) { return hipFree(p); }
 hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t) {
     std::lock_guard<std::mutex> lk(hipsim::launch_mu);
     memmove(d, s, n);
@@ -54,6 +81,12 @@ hipError_t hipEventDestroy(hipEvent_t e) { delete[] (char *)e; return hipSuccess
 hipError_t hipGetLastError() { return hipSuccess; }
 const char *hipGetErrorString(hipError_t) { return "simulated"; }
 long hipsim_live_allocs() { return g_live_allocs.load(); }
+long hipsim_live_device_bytes() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_live_dev_bytes;
+}
+// While set, relaxation rounds make no progress (queries stay unconverged).
+void hipsim_stall(bool on) { g_stall.store(on); }
 
 namespace stn {
 
@@ -117,7 +150,7 @@ hipError_t launch_slot_start(const VorParams &P, uint32_t slot, const uint32_t *
 
 hipError_t launch_round(const VorParams &P, uint32_t, uint32_t, hipStream_t) {
     std::lock_guard<std::mutex> lk(sim_mu);
-    if (P.pass->all_done) return hipSuccess;
+    if (P.pass->all_done || g_stall.load()) return hipSuccess;
     bool any = false;
     for (uint32_t q = 0; q < P.nslots; q++) {
         if (!P.slot.active[q]) continue;
@@ -158,7 +191,7 @@ hipError_t launch_compact(const CompactParams &C, uint32_t, uint32_t, hipStream_
         uint32_t m = 0;
         for (uint32_t j = 1; j < k && m < C.out_cap[slot]; j++, m++) {
             C.out_idx[slot][m] = (uint32_t)((uint64_t)j * (j - 1) / 2);  // pair (0, j)
-            C.out_val[slot][m] = ((uint64_t)j << 32) | 0u;
+            if (C.out_val[slot]) C.out_val[slot][m] = ((uint64_t)j << 32) | 0u;
         }
         C.out_cnt[slot] = m;
     }

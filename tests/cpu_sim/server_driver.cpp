@@ -1,6 +1,7 @@
 // Drives the library's host code against the simulated runtime: graph upload
 // and validation, batched solves, and the server under concurrent clients.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <thread>
 #include <vector>
@@ -9,6 +10,8 @@
 #include "steiner.h"
 
 long hipsim_live_allocs();
+long hipsim_live_device_bytes();
+void hipsim_stall(bool on);
 
 // The renumbering's maps against the caller's CSR: perm is a permutation by
 // non-increasing degree and inv its inverse; every internal entry is a caller
@@ -77,6 +80,154 @@ static bool ell_ok(const steiner_graph *g) {
             return 1;                                                       \
         }                                                                   \
     } while (0)
+
+// Everything a server holds on the device is its budget: fixed + slots * slot_bytes + pool, allocated exactly.
+// A waiter past its timeout gets ETIMEDOUT and can wait again; a waiter blocked at destroy gets ECANCELED.
+static int server_memory_and_waits(steiner_graph *g) {
+    const long before = hipsim_live_device_bytes();
+    steiner_server *srv = nullptr;
+    const uint64_t budget = 5ull << 20;
+    CHECK(steiner_server_create(g, budget, 7, nullptr, &srv) == STEINER_OK);
+    uint64_t fixed = 0, slot = 0, pool = 0;
+    uint32_t slots = 0;
+    CHECK(steiner_server_memory(srv, &fixed, &slot, &slots, &pool) == STEINER_OK);
+    CHECK(slots == 7 && fixed + slots * slot + pool == budget);
+    CHECK((uint64_t)(hipsim_live_device_bytes() - before) <= budget);
+    CHECK(steiner_server_query_bytes(srv, 5) > slot);
+    // a request whose pool region exceeds the pool is refused at submit
+    std::vector<uint32_t> all(g->n);
+    for (uint32_t v = 0; v < g->n; v++) all[v] = v;
+    uint64_t t = 0;
+    {
+        steiner_server *small = nullptr;
+        const uint64_t one = steiner_server_query_bytes(srv, 2) + fixed;
+        CHECK(steiner_server_create(g, one + 4096, 3, nullptr, &small) == STEINER_OK);
+        CHECK(steiner_server_submit(small, all.data(), g->n, &t) == STEINER_ENOMEM);
+        CHECK(steiner_server_destroy(small) == STEINER_OK);
+    }
+    hipsim_stall(true);
+    const uint32_t s1[] = {3, 9, 27};
+    CHECK(steiner_server_submit(srv, s1, 3, &t) == STEINER_OK);
+    steiner_result *r = nullptr;
+    CHECK(steiner_server_wait(srv, t, 2000, &r) == STEINER_ETIMEDOUT && r == nullptr);
+    hipsim_stall(false);
+    CHECK(steiner_server_wait(srv, t, -1, &r) == STEINER_OK && r != nullptr);
+    steiner_result_free(r);
+    CHECK(steiner_server_wait(srv, t, 0, &r) == STEINER_EINVAL);  // a ticket is consumed by its result
+    hipsim_stall(true);
+    uint64_t t2 = 0, t3 = 0;
+    const uint32_t s2[] = {1, 2, 40}, s3[] = {5, 6};
+    CHECK(steiner_server_submit(srv, s2, 3, &t2) == STEINER_OK);
+    CHECK(steiner_server_submit(srv, s3, 2, &t3) == STEINER_OK);
+    int rc2 = 0, rc3 = 0;
+    std::thread w2([&] {
+        steiner_result *x = nullptr;
+        rc2 = steiner_server_wait(srv, t2, -1, &x);
+    });
+    std::thread w3([&] {
+        steiner_result *x = nullptr;
+        rc3 = steiner_server_wait(srv, t3, 60000000, &x);
+    });
+    std::this_thread::sleep_for(std::chrono::milliseconds(100));
+    CHECK(steiner_server_destroy(srv) == STEINER_OK);
+    w2.join();
+    w3.join();
+    hipsim_stall(false);
+    CHECK(rc2 == STEINER_ECANCELED && rc3 == STEINER_ECANCELED);
+    CHECK(hipsim_live_device_bytes() == before);
+    return 0;
+}
+
+// A query holds at most STEINER_MAX_SEEDS distinct seeds: one more is EINVAL for solves and for the server.
+static int max_seeds(uint32_t) {
+    const uint32_t n = STEINER_MAX_SEEDS + 10;
+    std::vector<uint64_t> rp(n + 1);
+    std::vector<uint32_t> col, w;
+    for (uint32_t v = 0; v < n; v++) {
+        rp[v] = col.size();
+        if (v > 0) { col.push_back(v - 1); w.push_back(1); }
+        if (v + 1 < n) { col.push_back(v + 1); w.push_back(1); }
+    }
+    rp[n] = col.size();
+    steiner_graph *g = nullptr;
+    CHECK(steiner_graph_upload(n, col.size(), rp.data(), col.data(), w.data(), 0, nullptr, 0, &g) == STEINER_OK);
+    std::vector<uint32_t> seeds(STEINER_MAX_SEEDS + 1);
+    for (uint32_t i = 0; i < seeds.size(); i++) seeds[i] = i;
+    steiner_result *r = nullptr;
+    CHECK(steiner_solve(g, seeds.data(), (uint32_t)seeds.size(), nullptr, &r) == STEINER_EINVAL && r == nullptr);
+    std::vector<uint32_t> dup = seeds;  // duplicates do not count
+    dup.back() = 0;
+    steiner_server *srv = nullptr;
+    CHECK(steiner_server_create(g, 64ull << 20, 2, nullptr, &srv) == STEINER_OK);
+    uint64_t t = 0;
+    CHECK(steiner_server_submit(srv, seeds.data(), (uint32_t)seeds.size(), &t) == STEINER_EINVAL);
+    CHECK(steiner_server_destroy(srv) == STEINER_OK);
+    CHECK(steiner_graph_free(g) == STEINER_OK);
+    CHECK(hipsim_live_allocs() == 0);
+    return 0;
+}
+
+// Every device or pinned-host allocation of an upload, a solve, a batch and a server start fails in turn
+// (stn::set_fault_alloc_after): the call returns ENOMEM and, once the graph is freed, nothing is left allocated.
+static int injected_allocation_failures(const std::vector<uint64_t> &rp, const std::vector<uint32_t> &col,
+                                        const std::vector<uint32_t> &w) {
+    const uint32_t n = (uint32_t)rp.size() - 1;
+    const uint32_t seeds[] = {1, 30, 50, 7};
+    std::vector<std::vector<uint32_t>> sets = {{1, 5, 9}, {2, 30}, {0, 63, 10, 20, 40}};
+    std::vector<const uint32_t *> ptrs;
+    std::vector<uint32_t> ks;
+    for (auto &x : sets) { ptrs.push_back(x.data()); ks.push_back((uint32_t)x.size()); }
+    for (int what = 0; what < 4; what++) {  // upload, solve, batch, server
+        long points = -1;
+        for (long lim = 0; lim < 400 && points < 0; lim++) {
+            steiner_graph *g = nullptr;
+            stn::set_fault_alloc_after(what == 0 ? lim : -1);
+            int rc = steiner_graph_upload(n, col.size(), rp.data(), col.data(), w.data(), 0, nullptr, 0, &g);
+            if (what == 0) {
+                CHECK(rc == STEINER_OK || rc == STEINER_ENOMEM);
+                if (rc == STEINER_OK) points = lim;
+            } else {
+                CHECK(rc == STEINER_OK);
+                stn::set_fault_alloc_after(lim);
+                if (what == 1) {
+                    steiner_result *r = nullptr;
+                    rc = steiner_solve(g, seeds, 4, nullptr, &r);
+                    if (rc == STEINER_OK) steiner_result_free(r);
+                } else if (what == 2) {
+                    std::vector<steiner_result *> outs(sets.size(), nullptr);
+                    std::vector<int> st(sets.size());
+                    rc = steiner_solve_batch(g, (uint32_t)sets.size(), ptrs.data(), ks.data(), nullptr, outs.data(),
+                                             st.data());
+                    for (size_t i = 0; i < sets.size(); i++)
+                        if (rc == STEINER_OK) {
+                            CHECK(st[i] == STEINER_OK);
+                            steiner_result_free(outs[i]);
+                        }
+                } else {
+                    steiner_server *srv = nullptr;
+                    rc = steiner_server_create(g, 4ull << 20, 3, nullptr, &srv);
+                    if (rc == STEINER_OK) {
+                        uint64_t t = 0;
+                        steiner_result *r = nullptr;
+                        CHECK(steiner_server_submit(srv, seeds, 4, &t) == STEINER_OK);
+                        rc = steiner_server_wait(srv, t, -1, &r);
+                        if (rc == STEINER_OK) steiner_result_free(r);
+                        CHECK(steiner_server_destroy(srv) == STEINER_OK);
+                    }
+                }
+                CHECK(rc == STEINER_OK || rc == STEINER_ENOMEM);
+                if (rc == STEINER_OK) points = lim;
+            }
+            stn::set_fault_alloc_after(-1);
+            if (g) CHECK(steiner_graph_free(g) == STEINER_OK);
+            CHECK(hipsim_live_allocs() == 0);
+        }
+        CHECK(points > 0);
+        printf("injected allocation failures: operation %d fails cleanly at each of its %ld allocations\n", what,
+               points);
+    }
+    return 0;
+}
 
 int main() {
     const uint32_t n = 64;
@@ -195,14 +346,26 @@ int main() {
 
     // server: budget for 3 queries, 5 slots, 4 client threads
     steiner_server *srv = nullptr;
-    const uint64_t one = 13ull * n;
     CHECK(steiner_server_create(g, 10, 4, nullptr, &srv) == STEINER_EINVAL);
-    CHECK(steiner_server_create(g, 3 * (one + 4096), 5, nullptr, &srv) == STEINER_OK);
+    uint64_t fixed5 = 0, one = 0;
+    {
+        steiner_server *probe = nullptr;
+        CHECK(steiner_server_create(g, 64ull << 20, 5, nullptr, &probe) == STEINER_OK);
+        CHECK(steiner_server_memory(probe, &fixed5, nullptr, nullptr, nullptr) == STEINER_OK);
+        one = steiner_server_query_bytes(probe, 9);
+        CHECK(steiner_server_destroy(probe) == STEINER_OK);
+    }
+    CHECK(steiner_server_create(g, fixed5 + 3 * one + 4096, 5, nullptr, &srv) == STEINER_OK);
     uint64_t t = 0;
     CHECK(steiner_server_submit(srv, nullptr, 0, &t) == STEINER_EINVAL);
     std::vector<uint32_t> too_many(n);
     for (uint32_t v = 0; v < n; v++) too_many[v] = v;
-    CHECK(steiner_server_query_bytes(srv, 10) > one);
+    CHECK(steiner_server_query_bytes(srv, 40) > one && steiner_server_query_bytes(srv, 2) <= one);
+    {
+        uint32_t slots = 0;
+        CHECK(steiner_server_memory(srv, nullptr, nullptr, &slots, nullptr) == STEINER_OK);
+        CHECK(slots >= 3 && slots <= 5);
+    }
     int failures = 0;
     std::vector<std::thread> clients;
     for (int c = 0; c < 4; c++) {
@@ -233,8 +396,11 @@ int main() {
         CHECK(steiner_server_submit(srv, s, 3, &t) == STEINER_OK);
     }
     CHECK(steiner_server_destroy(srv) == STEINER_OK);
+    CHECK(server_memory_and_waits(g) == 0);
     CHECK(steiner_graph_free(g) == STEINER_OK);
     CHECK(hipsim_live_allocs() == 0);
+    CHECK(max_seeds(n) == 0);
+    CHECK(injected_allocation_failures(rp, col, w) == 0);
     printf("cpu_sim ok\n");
     return 0;
 }

@@ -122,6 +122,20 @@ def test_error_codes_and_edge_cases(stream):
     with st.Graph(g, 0, stream) as dg:
         assert gpu_code(dg.solve, np.array([], dtype=np.uint32))[0] == st.EINVAL
         assert gpu_code(dg.solve, [0, 4])[0] == st.EINVAL
+    # more distinct seeds than a query may hold (k(k-1)/2 pair indices must fit in 32 bits)
+    n = 100_000
+    path = W.from_edges(n, [(v, v + 1, 1) for v in range(n - 1)])
+    many = np.arange(92_683, dtype=np.uint32)
+    with st.Graph(path, 0, stream) as dg:
+        assert gpu_code(dg.solve, many)[0] == st.EINVAL
+        assert gpu_code(dg.solve_batch, [many[:3], many])[0] == st.OK  # per-query status
+        codes = [c for c, _ in dg.solve_batch([many[:3], many])]
+        assert codes == [st.OK, st.EINVAL]
+        srv = st.steiner_server_create(dg.handle, 1 << 30, 2)
+        try:
+            assert gpu_code(st.steiner_server_submit, srv, many)[0] == st.EINVAL
+        finally:
+            st.steiner_server_destroy(srv)
 
 
 def test_upload_validation(stream):

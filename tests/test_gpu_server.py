@@ -3,6 +3,7 @@ the same query alone and the oracle's, admission respects the memory budget,
 and error paths report the right codes."""
 import sys
 import threading
+import time
 
 import numpy as np
 import pytest
@@ -32,12 +33,26 @@ def graph():
     dg.close()
 
 
-def test_server_mix_equals_alone_and_oracle(graph):
+SERVER_OPTIONS = {
+    "default": None,
+    "delta1": dict(delta=1),
+    "delta50": dict(delta=50),
+    "split": dict(delta=50, flags=st.FLAG_SPLIT),
+    "no_local_queue": dict(local_iters=0xFFFFFFFF),
+    "split_chunky": dict(delta=7, flags=st.FLAG_SPLIT, small_max=1, chunk=64, local_iters=0xFFFFFFFF),
+}
+
+
+@pytest.mark.parametrize("opt", list(SERVER_OPTIONS))
+def test_server_mix_equals_alone_and_oracle(graph, opt):
+    """Queries seeded between rounds while other slots advance buckets, park
+    vertices and relax heavy edges: every served tree equals the oracle's and
+    the same query's solve alone, under each set of relaxation options."""
     g, cand, dg = graph
     ks = [3, 40, 2, 600, 17, 5, 250, 1, 90, 8, 33, 1200, 4, 64, 7, 150]
     sets = [W.sample(cand, k, master=11, stream=300 + q) for q, k in enumerate(ks)]
-    say("server: 16 queries, 5 slots")
-    srv = st.steiner_server_create(dg.handle, 4 << 30, 5)
+    say(f"server ({opt}): 16 queries, 5 slots")
+    srv = st.steiner_server_create(dg.handle, 4 << 30, 5, SERVER_OPTIONS[opt])
     try:
         tickets = [st.steiner_server_submit(srv, s) for s in sets]
         trees = [st.steiner_server_wait(srv, t) for t in tickets]
@@ -47,7 +62,7 @@ def test_server_mix_equals_alone_and_oracle(graph):
         ref = O.solve(g, s)
         assert ref.code == O.OK
         assert tree.edges == ref.edges and tree.total == ref.total, f"query {q} (k={ks[q]})"
-        alone = dg.solve(s)
+        alone = dg.solve(s, SERVER_OPTIONS[opt])
         assert alone.edges == tree.edges
 
 
@@ -83,12 +98,20 @@ def test_server_concurrent_clients(graph):
 
 def test_server_budget_and_errors(graph):
     g, cand, dg = graph
-    one = 13 * g.n
-    srv = st.steiner_server_create(dg.handle, 3 * one + (1 << 20), 64)
+    probe = st.steiner_server_create(dg.handle, 1 << 30, 64)
+    mem = st.steiner_server_memory(probe)
+    one = st.steiner_server_query_bytes(probe, 20)
+    st.steiner_server_destroy(probe)
+    assert mem["fixed_bytes"] + mem["slots"] * mem["slot_bytes"] + mem["pool_bytes"] == 1 << 30
+    assert mem["slot_bytes"] >= 14 * g.n
+    budget = mem["fixed_bytes"] + 3 * one + (1 << 16)
+    srv = st.steiner_server_create(dg.handle, budget, 64)
     try:
+        m = st.steiner_server_memory(srv)
+        assert m["slots"] == 3 and m["fixed_bytes"] + 3 * m["slot_bytes"] + m["pool_bytes"] == budget
         need = st.steiner_server_query_bytes(srv, 100)
-        assert need >= one + 8 * 100 * 99 // 2
-        # a query that alone exceeds the budget is refused at submit
+        assert need >= m["slot_bytes"] + 8 * 100 * 99 // 2
+        # a query whose pool region exceeds the whole pool is refused at submit
         with pytest.raises(st.SteinerError) as e:
             st.steiner_server_submit(srv, cand[:3000])
         assert e.value.code == st.ENOMEM
@@ -150,3 +173,37 @@ def test_server_fixed_stride_rows(graph):
             assert ref.code == O.OK
             assert tree.edges == ref.edges and tree.total == ref.total, f"query {q} (k={ks[q]})"
             assert gg.solve(s).edges == tree.edges
+
+
+def test_server_timeout_and_cancel(graph):
+    """A wait that runs out of time returns ETIMEDOUT and leaves the request
+    pending; waiters blocked when the server is destroyed get ECANCELED."""
+    g, cand, dg = graph
+    sets = [W.sample(cand, 1200, master=14, stream=600 + q) for q in range(40)]
+    srv = st.steiner_server_create(dg.handle, 4 << 30, 1)
+    codes = {}
+    try:
+        tickets = [st.steiner_server_submit(srv, s) for s in sets]
+        with pytest.raises(st.SteinerError) as e:
+            st.steiner_server_wait(srv, tickets[-1], 0)
+        assert e.value.code == st.ETIMEDOUT
+        first = st.steiner_server_wait(srv, tickets[0])  # still pending after the time-out elsewhere
+        assert first.edges == dg.solve(sets[0]).edges
+
+        def waiter(q):
+            try:
+                st.steiner_server_wait(srv, tickets[q])
+                codes[q] = st.OK
+            except st.SteinerError as ex:
+                codes[q] = ex.code
+
+        threads = [threading.Thread(target=waiter, args=(q,)) for q in range(35, 40)]
+        for th in threads:
+            th.start()
+        time.sleep(0.05)
+    finally:
+        st.steiner_server_destroy(srv)
+    for th in threads:
+        th.join(timeout=60)
+    assert sorted(codes) == list(range(35, 40))
+    assert all(c == st.ECANCELED for c in codes.values()), codes
