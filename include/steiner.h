@@ -163,6 +163,26 @@ int steiner_solve(steiner_graph *g, const uint32_t *seeds, uint32_t k, const ste
 int steiner_solve_batch(steiner_graph *g, uint32_t q, const uint32_t *const *seeds, const uint32_t *ks,
                         const steiner_options *opt, steiner_result **outs, int *status);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): steiner_solve
+ * without any device or pinned-host allocation and without creating streams
+ * or events.  Same kernels and the same result as steiner_solve with the same
+ * options (the relaxation is always host-stepped).  Every device buffer comes
+ * from one library-wide array of STEINER_NOALLOC_SCRATCH_BYTES on each device,
+ * which the library sets aside when it is loaded on that device and holds
+ * until the process ends; a solve that needs more (vertex state, frontier
+ * lists, pair table, tree scratch: about 80 B per vertex plus 8 B per seed
+ * pair) returns ENOMEM, and so do more than 8192 seeds (duplicates
+ * included).  The tree goes to the caller's HOST arrays a, b, w of capacity
+ * cap (sorted by (a, b, w)), its size to *m and D to *total; ENOMEM with *m
+ * set if cap is too small.  Calls in one process run one at a time (the array
+ * keeps the last call's contents; each call re-initialises what it reads);
+ * calls that overlapped on one GPU would race on the array.  The host thread
+ * waits for the solve to finish. */
+#define STEINER_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int steiner_solve_noalloc(steiner_graph *g, const uint32_t *seeds, uint32_t k, const steiner_options *opt,
+                          uint64_t cap, uint64_t *m, uint32_t *a, uint32_t *b, uint32_t *w, uint64_t *total);
+
 /* Tree edges (a < b, sorted by (a, b, w)); pointers stay valid until
  * steiner_result_free. */
 int steiner_result_edges(const steiner_result *r, uint64_t *m, const uint32_t **a, const uint32_t **b,

@@ -40,7 +40,7 @@ DRIVER_DEFAULT, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
 
 EXPORTS = [
     "steiner_graph_upload", "steiner_graph_upload_device", "steiner_graph_free", "steiner_graph_tune", "steiner_solve",
-    "steiner_solve_batch", "steiner_result_edges", "steiner_result_total", "steiner_result_stats",
+    "steiner_solve_noalloc", "steiner_solve_batch", "steiner_result_edges", "steiner_result_total", "steiner_result_stats",
     "steiner_result_free", "steiner_voronoi", "steiner_boundary", "steiner_server_create",
     "steiner_server_submit", "steiner_server_wait", "steiner_server_query_bytes", "steiner_server_memory",
     "steiner_server_destroy",
@@ -87,6 +87,7 @@ def load(path: str | None = None):
         "steiner_graph_free": (i32, [vp]),
         "steiner_graph_tune": (i32, [vp, vp, u32, vp]),
         "steiner_solve": (i32, [vp, vp, u32, vp, vp]),
+        "steiner_solve_noalloc": (i32, [vp, vp, u32, vp, u64, vp, vp, vp, vp, vp]),
         "steiner_solve_batch": (i32, [vp, u32, vp, vp, vp, vp, vp]),
         "steiner_result_edges": (i32, [vp, vp, vp, vp, vp]),
         "steiner_result_total": (u64, [vp]),
@@ -229,6 +230,26 @@ def steiner_solve(g: int, seeds, options=None) -> Tree:
     _check(load().steiner_solve(g, s.ctypes.data if len(s) else None, len(s), o[0] if o else None,
                                 ctypes.byref(out)))
     return _take_result(out.value)
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def steiner_solve_noalloc(g: int, seeds, cap: int, options=None) -> Tree:
+    """steiner_solve without allocation inside the library: the tree lands in
+    host arrays of capacity `cap` allocated here by the caller's side."""
+    s = _u32(seeds)
+    a = np.empty(max(cap, 1), dtype=np.uint32)
+    b = np.empty(max(cap, 1), dtype=np.uint32)
+    w = np.empty(max(cap, 1), dtype=np.uint32)
+    m = ctypes.c_uint64()
+    tot = ctypes.c_uint64()
+    o = _opts(options)
+    _check(load().steiner_solve_noalloc(g, s.ctypes.data if len(s) else None, len(s), o[0] if o else None, cap,
+                                        ctypes.byref(m), a.ctypes.data, b.ctypes.data, w.ctypes.data,
+                                        ctypes.byref(tot)))
+    k = m.value
+    return Tree(a[:k].copy(), b[:k].copy(), w[:k].copy(), tot.value, {})
 
 
 def steiner_solve_batch(g: int, seed_sets, options=None):

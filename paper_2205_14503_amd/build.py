@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsteiner.so")
-SOURCES = ["kernels.hip", "engine.cpp", "pass.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "engine.cpp", "pass.cpp", "server.cpp", "noalloc.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -651,6 +651,7 @@ static int graph_create(uint32_t n, uint64_t nnz, int device, void *stream, stei
     g->nnz = nnz;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) g->cu_count = prop.multiProcessorCount;
+    noalloc_setup(device);
     *out = g;
     return STEINER_OK;
 }

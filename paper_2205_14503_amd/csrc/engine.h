@@ -213,13 +213,27 @@ int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t
                  double *ms_expand);
 // Bytes of the MST's scratch for k seeds and a G'1 of m entries.
 size_t mst_scratch_bytes(uint32_t k, uint64_t m);
+// Device buffers of Steps 3-6 for one query: the MST's scratch (mst_scratch_bytes; its first 16 bytes
+// receive the chosen cross-cell edges' count at [2] and the tree's edge count at [3]), the vertex marks
+// (all zero on entry and again on exit) and the output edges (a, b, w at out, out + n, out + 2n).
+struct TreeBufs {
+    uint8_t *mst;
+    uint32_t *mark, *out;
+};
+// Launches Steps 3-6 of one query on st (see tree_from_g1); ev_mid (optional) is recorded between the MST and
+// the expansion.
+int launch_tree(const steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
+                const uint64_t *pt, const uint32_t *tr, const uint32_t *g1_idx, uint32_t m, bool pred_ready,
+                const TreeBufs &tb, hipEvent_t ev_mid);
 // Pair-table ranks of a query's seeds (see pair_slot): rk[i] is the rank of
 // seed index i among the seeds ordered by internal id and rk[k + r] the seed
 // index of rank r.  Empty when the graph keeps the caller's order (identity).
 void seed_ranks(const steiner_graph *g, const std::vector<uint32_t> &S, std::vector<uint32_t> &rk);
 void pair_from_index(uint64_t p, uint32_t *i, uint32_t *j);
 int canon_seeds(const steiner_graph *g, const uint32_t *seeds, uint32_t k, std::vector<uint32_t> &S);
-uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chunk);
+uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chunk, bool remember = true);
+// Looks up the allocation-free solve's device scratch on `device` (the current device) once per device.
+void noalloc_setup(int device);
 // Fills the pass parameters shared by every driver for Q slots.
 void bind_state(VorParams &P, const Options &o, uint64_t cap_s, uint64_t cap_b);
 

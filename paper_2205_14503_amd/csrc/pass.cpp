@@ -10,8 +10,8 @@
 namespace stn {
 
 // Chunks of the rows above small_max (sizes the chunk lists); one O(n) host
-// pass per (small_max, chunk) and graph, remembered.
-uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chunk) {
+// pass per (small_max, chunk) and graph, remembered unless `remember` is false.
+uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chunk, bool remember) {
     const uint64_t memo_key = ((uint64_t)small_max << 32) | chunk;
     {
         std::lock_guard<std::mutex> lk(g->memo_mu);
@@ -23,6 +23,7 @@ uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chu
         uint64_t d = g->h_rp[v + 1] - g->h_rp[v];
         if (d > small_max) t += (d + chunk - 1) / chunk;
     }
+    if (!remember) return t;
     std::lock_guard<std::mutex> lk(g->memo_mu);
     g->chunk_memo[memo_key] = t;
     return t;
@@ -197,15 +198,12 @@ void TailScratch::release() {
     mark_n = 0;
 }
 
-int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
-                 const uint64_t *pt, const uint32_t *tr, const uint32_t *g1_idx, uint32_t m, bool pred_ready,
-                 TailScratch &ts, uint8_t *mst_buf, std::unique_ptr<steiner_result> &out, double *ms_mst,
-                 double *ms_expand) {
+int launch_tree(const steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
+                const uint64_t *pt, const uint32_t *tr, const uint32_t *g1_idx, uint32_t m, bool pred_ready,
+                const TreeBufs &tb, hipEvent_t ev_mid) {
     const uint32_t n = g->n;
-    int rc;
-    if ((rc = ts.prepare(n, k, m, mst_buf == nullptr, st))) return rc;
     const size_t k4 = ((size_t)k * 4 + 255) & ~(size_t)255, m4 = ((size_t)m * 4 + 255) & ~(size_t)255;
-    uint8_t *base = mst_buf ? mst_buf : ts.mst.as<uint8_t>();
+    uint8_t *base = tb.mst;
     MstParams M{};
     M.pt = pt;
     M.tr = tr;
@@ -224,8 +222,8 @@ int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t
     EP.sel_e = M.sel;
     EP.nsel = M.hdr + 2;
     EP.nsel_max = k - 1;
-    EP.mark = ts.mark.as<uint32_t>();
-    EP.oa = ts.out.as<uint32_t>();
+    EP.mark = tb.mark;
+    EP.oa = tb.out;
     EP.ob = EP.oa + n;
     EP.ow = EP.oa + 2 * (size_t)n;
     EP.ocnt = M.hdr + 3;
@@ -233,14 +231,27 @@ int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t
     const uint32_t emit_grid = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>((uint64_t)std::max(1, g->cu_count) * 8, (((uint64_t)n + 3) / 4 + 255) / 256));
     // Step 3 (MST of G'1), Step 4 (its kept cross-cell edges), Steps 5-6 (pred walks)
+    int rc = hip_check(launch_mst(M, g1_idx, m, st), "mst");
+    if (!rc && ev_mid) rc = hip_check(hipEventRecord(ev_mid, st), "event");
+    if (!rc) rc = hip_check(launch_expand(EP, emit_grid, st), "expand");
+    return rc;
+}
+
+int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
+                 const uint64_t *pt, const uint32_t *tr, const uint32_t *g1_idx, uint32_t m, bool pred_ready,
+                 TailScratch &ts, uint8_t *mst_buf, std::unique_ptr<steiner_result> &out, double *ms_mst,
+                 double *ms_expand) {
+    const uint32_t n = g->n;
+    int rc;
+    if ((rc = ts.prepare(n, k, m, mst_buf == nullptr, st))) return rc;
+    TreeBufs tb{mst_buf ? mst_buf : ts.mst.as<uint8_t>(), ts.mark.as<uint32_t>(), ts.out.as<uint32_t>()};
+    const uint32_t *hdr = (const uint32_t *)tb.mst;
     const bool timed = ms_mst || ms_expand;
     rc = timed ? hip_check(hipEventRecord(ts.ev[0], st), "event") : STEINER_OK;
-    if (!rc) rc = hip_check(launch_mst(M, g1_idx, m, st), "mst");
-    if (!rc && timed) rc = hip_check(hipEventRecord(ts.ev[1], st), "event");
-    if (!rc) rc = hip_check(launch_expand(EP, emit_grid, st), "expand");
+    if (!rc) rc = launch_tree(g, st, key, pred, k, pt, tr, g1_idx, m, pred_ready, tb, timed ? ts.ev[1] : nullptr);
     if (!rc && timed) rc = hip_check(hipEventRecord(ts.ev[2], st), "event");
     uint32_t *h = ts.host.as<uint32_t>();
-    if (!rc) rc = hip_check(hipMemcpyAsync(h, M.hdr, 16, hipMemcpyDeviceToHost, st), "D2H counts");
+    if (!rc) rc = hip_check(hipMemcpyAsync(h, hdr, 16, hipMemcpyDeviceToHost, st), "D2H counts");
     if (!rc) rc = hip_check(hipStreamSynchronize(st), "tail sync");
     if (rc) {
         ts.mark_n = 0;  // the marks may be left set
@@ -262,9 +273,10 @@ int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t
     // the edge arrays into pinned memory, one synchronisation
     if ((rc = ts.host.ensure(((size_t)m_out * 3 + 16) * 4))) return rc;
     uint32_t *ha = ts.host.as<uint32_t>() + 16, *hb = ha + m_out, *hw = hb + m_out;
-    rc = hip_check(hipMemcpyAsync(ha, EP.oa, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
-    if (!rc) rc = hip_check(hipMemcpyAsync(hb, EP.ob, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
-    if (!rc) rc = hip_check(hipMemcpyAsync(hw, EP.ow, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+    rc = hip_check(hipMemcpyAsync(ha, tb.out, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+    if (!rc) rc = hip_check(hipMemcpyAsync(hb, tb.out + n, (size_t)m_out * 4, hipMemcpyDeviceToHost, st), "D2H edges");
+    if (!rc) rc = hip_check(hipMemcpyAsync(hw, tb.out + 2 * (size_t)n, (size_t)m_out * 4, hipMemcpyDeviceToHost, st),
+                            "D2H edges");
     if (!rc) rc = hip_check(hipStreamSynchronize(st), "D2H edges");
     if (rc) return rc;
     // Step 7: canonical order (a, b, w) and D.  A tree has one edge per vertex

@@ -79,6 +79,10 @@ hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 hipError_t hipEventElapsedTime(float *m, hipEvent_t, hipEvent_t) { *m = 0.f; return hipSuccess; }
 hipError_t hipEventDestroy(hipEvent_t e) { delete[] (char *)e; return hipSuccess; }
 hipError_t hipGetLastError() { return hipSuccess; }
+hipError_t hipGetSymbolAddress(void **p, const void *sym) {
+    *p = const_cast<void *>(sym);
+    return hipSuccess;
+}
 const char *hipGetErrorString(hipError_t) { return "simulated"; }
 long hipsim_live_allocs() { return g_live_allocs.load(); }
 long hipsim_live_device_bytes() {

@@ -41,6 +41,7 @@ struct hipDeviceProp_t {
 };
 #define hipStreamNonBlocking 1
 #define hipHostMallocDefault 0
+#define HIP_SYMBOL(x) (&(x))
 
 namespace hipsim {
 extern std::mutex launch_mu;  // one simulated kernel at a time
@@ -84,4 +85,5 @@ hipError_t hipEventSynchronize(hipEvent_t);
 hipError_t hipEventElapsedTime(float *, hipEvent_t, hipEvent_t);
 hipError_t hipEventDestroy(hipEvent_t);
 hipError_t hipGetLastError();
+hipError_t hipGetSymbolAddress(void **, const void *);
 const char *hipGetErrorString(hipError_t);

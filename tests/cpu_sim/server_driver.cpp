@@ -344,6 +344,40 @@ int main() {
         steiner_result_free(outs[i]);
     }
 
+    // the allocation-free solve: same tree as steiner_solve, twice in a row (the second smaller), no allocation
+    {
+        const uint32_t s1[] = {40, 3, 17, 3, 60, 25}, s2[] = {9, 2};
+        for (int rep = 0; rep < 2; rep++) {
+            const uint32_t *sd = rep ? s2 : s1;
+            const uint32_t kk = rep ? 2 : 6;
+            steiner_result *r = nullptr;
+            CHECK(steiner_solve(g, sd, kk, nullptr, &r) == STEINER_OK);
+            uint64_t m = 0;
+            const uint32_t *ra, *rb, *rw;
+            CHECK(steiner_result_edges(r, &m, &ra, &rb, &rw) == STEINER_OK);
+            const long live = hipsim_live_allocs();
+            std::vector<uint32_t> a(n), b(n), ww(n);
+            uint64_t m2 = 0, tot = 0;
+            CHECK(steiner_solve_noalloc(g, sd, kk, nullptr, n, &m2, a.data(), b.data(), ww.data(), &tot) == STEINER_OK);
+            CHECK(hipsim_live_allocs() == live);
+            CHECK(m2 == m && tot == steiner_result_total(r));
+            for (uint64_t t = 0; t < m; t++) CHECK(a[t] == ra[t] && b[t] == rb[t] && ww[t] == rw[t]);
+            if (m) {
+                uint64_t m3 = 0;
+                CHECK(steiner_solve_noalloc(g, sd, kk, nullptr, m - 1, &m3, a.data(), b.data(), ww.data(), &tot) ==
+                      STEINER_ENOMEM);
+                CHECK(m3 == m);
+            }
+            steiner_result_free(r);
+        }
+        std::vector<uint32_t> many(9000, 1);
+        uint64_t m = 0, tot = 0;
+        CHECK(steiner_solve_noalloc(g, many.data(), 9000, nullptr, 0, &m, nullptr, nullptr, nullptr, &tot) ==
+              STEINER_ENOMEM);
+        const uint32_t bad[] = {1, 64};
+        CHECK(steiner_solve_noalloc(g, bad, 2, nullptr, 0, &m, nullptr, nullptr, nullptr, &tot) == STEINER_EINVAL);
+    }
+
     // server: budget for 3 queries, 5 slots, 4 client threads
     steiner_server *srv = nullptr;
     CHECK(steiner_server_create(g, 10, 4, nullptr, &srv) == STEINER_EINVAL);

@@ -17,7 +17,7 @@ def test_host_logic_under_sanitizer(tmp_path, sanitizer):
     exe = str(tmp_path / f"sim_{sanitizer}")
     cmd = ["g++", "-std=c++17", "-O1", "-g", f"-fsanitize={sanitizer}", "-fno-omit-frame-pointer",
            "-I" + SIM, "-I" + CSRC, "-I" + os.path.join(ROOT, "include"), "-x", "c++",
-           os.path.join(CSRC, "engine.cpp"), os.path.join(CSRC, "pass.cpp"), os.path.join(CSRC, "server.cpp"),
+           os.path.join(CSRC, "engine.cpp"), os.path.join(CSRC, "pass.cpp"), os.path.join(CSRC, "server.cpp"), os.path.join(CSRC, "noalloc.cpp"),
            os.path.join(SIM, "fake_runtime.cpp"), os.path.join(SIM, "server_driver.cpp"), "-lpthread", "-o", exe]
     subprocess.run(cmd, check=True)
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=1")
