@@ -109,6 +109,10 @@ typedef struct steiner_stats {
      * moved to the next round's list, vertices parked beyond their bucket,
      * frontier items expanded. */
     uint64_t relax_attempts, relax_atomics, relax_improved, pushes_local, pushes_next, parked, items;
+    /* With STEINER_FLAG_COUNTERS, the boundary scan (Step 2): CSR entries
+     * read, neighbour keys gathered, cross-cell candidates (each reads its
+     * pair's current entry), atomicMins issued on the pair table. */
+    uint64_t scan_entries, scan_gathers, scan_candidates, scan_atomics;
 } steiner_stats;
 
 /* Upload flags. */

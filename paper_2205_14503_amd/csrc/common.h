@@ -68,6 +68,7 @@ struct Counters {
     // atomicMins issued, improvements, local-queue pushes, next-round pushes,
     // parked vertices, items expanded
     unsigned long long ev[8];
+    unsigned long long scan_ev[4];  // boundary-scan events (counting mode), see ScanParams::ev
 };
 constexpr uint32_t ROUND_GROUPS = 8;
 enum { EV_ATTEMPT = 0, EV_ATOMIC, EV_IMPROVED, EV_LOCAL, EV_GLOBAL, EV_PARK, EV_ITEMS, EV_N };
@@ -95,6 +96,10 @@ struct DevGraph {
     const uint32_t *heavy_chunk_off;
     uint32_t scan_heavy;
     uint32_t scan_chunk;
+    // 1 when the boundary scan may read each edge from its larger internal id: the graph was renumbered by
+    // degree (the heavy rows are the vertices below nheavy, hub keys sit on few lines) and every entry
+    // carries its edge id (eo)
+    uint32_t reverse_scan;
     // Internal vertex order.  Null when the ids are the caller's; otherwise
     // the graph was renumbered at upload and results are stated in the
     // caller's ids and CSR offsets: perm[v] is the caller's id of internal

@@ -626,6 +626,9 @@ static int finish_graph(steiner_graph *g, const uint64_t *d_rp64, const uint32_t
     dg.inv = g->d_inv;
     dg.eo = g->d_eo;
     dg.onew = g->d_onew;
+    bool prefix = true;
+    for (uint32_t h = 0; h < hrows.size() && prefix; h++) prefix = hrows[h] == h;
+    dg.reverse_scan = (g->reordered && g->d_eo && prefix && !std::getenv("STEINER_FORWARD_SCAN")) ? 1u : 0u;
     const double avg_w = nnz ? (double)wsum / (double)nnz : 1.0;
     const double avg_deg = n ? (double)nnz / (double)n : 1.0;
     // the classic bucket width (about the mean weight over the mean degree) is one of the tuner's

@@ -16,7 +16,11 @@ struct ScanParams {
     uint32_t *slot_err;    // [slots] ERR_DIST_OVERFLOW / ERR_SUM_OVERFLOW per query
     uint32_t with_pred;    // 1: pred of every vertex; 0: pred of rows above scan_heavy only (the tree
                            // expansion finds the others), and each edge's key gathered from one side only
+    unsigned long long *ev; // null, or SCAN_EV_N event counts (summed over the scanned slots)
 };
+// Boundary-scan event counters: CSR entries read, neighbour keys gathered, cross-cell candidates (each reads
+// its pair-table entry), atomicMins issued on the pair table.
+enum { SCAN_EV_ENTRIES = 0, SCAN_EV_GATHERS, SCAN_EV_CANDIDATES, SCAN_EV_ATOMICS, SCAN_EV_N };
 
 struct CompactParams {
     uint64_t *const *pt;        // per-slot pair tables

@@ -1059,6 +1059,7 @@ __global__ void k_pass_reset(VorParams P) {
         P.cnt->abort = 0;
         P.cnt->blocks_done = 0;
         for (int i = 0; i < EV_N; i++) P.cnt->ev[i] = 0;
+        for (int i = 0; i < 4; i++) P.cnt->scan_ev[i] = 0;
     }
     for (uint32_t i = t; i < ROUND_GROUPS * 32; i += gridDim.x * blockDim.x) P.cnt->grp_done[i] = 0;
     for (uint32_t q = t; q < P.nslots; q += gridDim.x * blockDim.x) {
@@ -1164,21 +1165,24 @@ DEVI void set_err(uint32_t *err, uint32_t bit) {
 // Cross-cell candidate of the edge of entry e, row -> u (row < u); ra is
 // the pair-table rank of the row's cell.  The edge id is loaded only if the
 // sum does not already lose to the pair's current entry.
-DEVI void boundary_candidate(const DevGraph &g, uint64_t *pt, const uint32_t *tr, uint32_t *err, uint64_t krow,
-                             uint32_t ra, uint64_t ku, uint32_t w, uint32_t e) {
+// Returns 0 (no candidate), 1 (a candidate that lost to the entry) or 2 (an atomicMin issued).
+DEVI int boundary_candidate(const DevGraph &g, uint64_t *pt, const uint32_t *tr, uint32_t *err, uint64_t krow,
+                            uint32_t ra, uint64_t ku, uint32_t w, uint32_t e) {
     const uint32_t i1 = (uint32_t)krow, i2 = (uint32_t)ku;
-    if (i1 == i2) return;
+    if (i1 == i2) return 0;
     const uint64_t bsum = (krow >> 32) + (uint64_t)w + (ku >> 32);
     if (bsum >= (1ull << 32)) {
         set_err(err, ERR_SUM_OVERFLOW);
-        return;
+        return 0;
     }
     const uint64_t rb = tr ? tr[i2] : i2, lo = min((uint64_t)ra, rb), hi = max((uint64_t)ra, rb);
     uint64_t *p = pt + hi * (hi - 1) / 2 + lo;
     const uint64_t cur = *p;
-    if (bsum > (cur >> 32)) return;
+    if (bsum > (cur >> 32)) return 1;
     const uint64_t val = (bsum << 32) | edge_id(g, e);
-    if (val < cur) atomicMin((unsigned long long *)p, (unsigned long long)val);
+    if (val >= cur) return 1;
+    atomicMin((unsigned long long *)p, (unsigned long long)val);
+    return 2;
 }
 
 // One wave scans the rows of group grp (64 consecutive vertices of at most
@@ -1189,10 +1193,26 @@ DEVI void boundary_candidate(const DevGraph &g, uint64_t *pt, const uint32_t *tr
 // rows included, which still sees every edge once for the overflow test.
 constexpr int SCAN_UNROLL = 2;
 
+// Adds the wave's per-lane event counts to the scan counters (counting mode).
+DEVI void scan_count(unsigned long long *ev, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    const uint32_t v[SCAN_EV_N] = {a, b, c, d};
+#pragma unroll
+    for (int i = 0; i < SCAN_EV_N; i++) {
+        uint32_t x = v[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o, 64);
+        if (lane() == 0 && x) atomicAdd(ev + i, (unsigned long long)x);
+    }
+}
+
+// REV: the lazy scan of a renumbered graph, each edge read from its larger id (the gathered keys are hub
+// keys); COUNT: event counters.
+template <bool REV, bool COUNT>
 DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *pred, uint64_t *pt, const uint32_t *tr,
-                           uint32_t *err, uint32_t grp, ScanWave *L) {
+                           uint32_t *err, uint32_t *heavy_pe, uint32_t grp, ScanWave *L) {
     const uint32_t n = S.g.n, ln = lane();
-    const bool wp = S.with_pred != 0;
+    const bool wp = !REV && S.with_pred != 0;
+    constexpr bool rev = REV;
     const uint32_t row = grp * 64 + ln;
     uint64_t kv = KEY_INF;
     uint32_t beg = 0, deg = 0, found = 1;
@@ -1227,6 +1247,7 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
     L->rank[ln] = (tr && kv != KEY_INF) ? tr[(uint32_t)kv] : (uint32_t)kv;
     L->key[ln] = kv;
     wave_sync();
+    uint32_t n_ent = 0, n_gat = 0, n_cand = 0, n_atom = 0;  // event counts (counting mode)
     // SCAN_UNROLL independent 64-entry steps per iteration, each level's loads issued for all of them
     // before any is used (idle lanes read entry / vertex / slot 0), so one latency chain covers them all.
     for (uint32_t base = 0; base < total; base += 64 * SCAN_UNROLL) {
@@ -1258,7 +1279,7 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
         }
 #pragma unroll
         for (int s = 0; s < SCAN_UNROLL; s++) {
-            side[s] = valid[s] && L->row[jj[s]] < u[s];
+            side[s] = valid[s] && (rev ? u[s] < L->row[jj[s]] : L->row[jj[s]] < u[s]);
             need[s] = valid[s] && (wp || side[s]);
             ku[s] = key[need[s] ? u[s] : 0u];
         }
@@ -1270,6 +1291,10 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
             if (wp && valid[s] && !L->found[jj[s]] && ku[s] != KEY_INF && (uint32_t)ku[s] == (uint32_t)kr &&
                 (ku[s] >> 32) + w[s] == (kr >> 32))
                 atomicMin(&L->best[jj[s]], caller_id(S.g, u[s]));
+            // reversed: this row may be the pred of a heavy neighbour (heavy rows are the ids below nheavy)
+            if (rev && u[s] < S.g.nheavy && ku[s] != KEY_INF && kr != KEY_INF && (uint32_t)ku[s] == (uint32_t)kr &&
+                (kr >> 32) + w[s] == (ku[s] >> 32))
+                atomicMin(heavy_pe + u[s], caller_id(S.g, L->row[jj[s]]));
         }
         // boundary candidates: the pair slots, then the current values, then the winners' atomics
         uint64_t *slot[SCAN_UNROLL], bsum[SCAN_UNROLL], cur[SCAN_UNROLL];
@@ -1292,19 +1317,29 @@ DEVI void scan_light_group(const ScanParams &S, const uint64_t *key, uint32_t *p
         for (int s = 0; s < SCAN_UNROLL; s++) cur[s] = *slot[s];
 #pragma unroll
         for (int s = 0; s < SCAN_UNROLL; s++) {
+            if (COUNT) {
+                n_ent += valid[s];
+                n_gat += need[s];
+                n_cand += cand[s];
+            }
             if (!cand[s] || bsum[s] > (cur[s] >> 32)) continue;
             const uint64_t val = (bsum[s] << 32) | edge_id(S.g, e[s]);
-            if (val < cur[s]) atomicMin((unsigned long long *)slot[s], (unsigned long long)val);
+            if (val < cur[s]) {
+                atomicMin((unsigned long long *)slot[s], (unsigned long long)val);
+                if (COUNT) n_atom++;
+            }
         }
     }
     wave_sync();
     if (wp && !found) pred[row] = L->best[ln] == NONE ? NONE : internal_id(S.g, L->best[ln]);
+    if (COUNT) scan_count(S.ev, n_ent, n_gat, n_cand, n_atom);
 }
 
 // One wave scans one chunk of a row above scan_heavy: boundary candidates and
 // the smallest caller id of a qualifying neighbour (atomicMin into heavy_pe).
 // An unreached row only checks its edges a -> b, a < b, for the overflow test
 // (without pred; with pred every reached row checks all of its own entries).
+template <bool REV, bool COUNT>
 DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *pt, const uint32_t *tr, uint32_t *err,
                            uint32_t *heavy_pe, uint32_t lc) {
     // heavy row h owning chunk lc: largest h with heavy_chunk_off[h] <= lc
@@ -1320,14 +1355,55 @@ DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *p
     const uint32_t beg = S.g.rp[row] + c * S.g.scan_chunk;
     const uint32_t lim = S.g.rp[row + 1];
     const uint32_t end = (lim - beg > S.g.scan_chunk) ? beg + S.g.scan_chunk : lim;
+    uint32_t n_ent = 0, n_gat = 0, n_cand = 0, n_atom = 0;  // event counts (counting mode)
+    if (REV) {
+        // Each edge is read from its larger id, so this row takes only its entries to smaller ids (other heavy
+        // rows; a sorted prefix of the row): candidates, the overflow test, and the pred minima of both ends
+        // (every entry to a larger id is seen from that neighbour's row).
+        const bool is_seed = kv != KEY_INF && (kv >> 32) == 0;
+        const uint32_t ra = (tr && kv != KEY_INF) ? tr[(uint32_t)kv] : (uint32_t)kv;
+        uint32_t best = NONE;
+        for (uint32_t e0 = beg; e0 < end; e0 += 64) {
+            const uint32_t e = e0 + lane();
+            const uint2 a = S.g.adj[e < end ? e : beg];
+            const bool on = e < end && a.x < row;
+            if (__ballot(on) == 0) break;  // sorted row: the rest is above row
+            if (!on) continue;
+            n_ent++;
+            n_gat++;
+            const uint64_t ku = key[a.x];
+            if ((ku == KEY_INF) != (kv == KEY_INF)) {
+                set_err(err, ERR_DIST_OVERFLOW);
+                continue;
+            }
+            if (kv == KEY_INF) continue;
+            if ((uint32_t)ku == (uint32_t)kv) {
+                if (!is_seed && (ku >> 32) + a.y == (kv >> 32)) best = min(best, caller_id(S.g, a.x));
+                if ((kv >> 32) + a.y == (ku >> 32)) atomicMin(heavy_pe + a.x, caller_id(S.g, row));
+            } else {
+                const int c = boundary_candidate(S.g, pt, tr, err, kv, ra, ku, a.y, e);
+                n_cand += c != 0;
+                n_atom += c == 2;
+            }
+        }
+        best = wave_min(best);
+        if (lane() == 0 && best != NONE) atomicMin(heavy_pe + h, best);
+        if (COUNT) scan_count(S.ev, n_ent, n_gat, n_cand, n_atom);
+        return;
+    }
     if (kv == KEY_INF) {
         for (uint32_t e0 = beg; e0 < end; e0 += 64) {
             const uint32_t e = e0 + lane();
             if (e < end) {
                 const uint32_t u = S.g.adj[e].x;
-                if (row < u && key[u] != KEY_INF) set_err(err, ERR_DIST_OVERFLOW);
+                n_ent++;
+                if (row < u) {
+                    n_gat++;
+                    if (key[u] != KEY_INF) set_err(err, ERR_DIST_OVERFLOW);
+                }
             }
         }
+        if (COUNT) scan_count(S.ev, n_ent, n_gat, 0, 0);
         return;
     }
     const bool is_seed = (kv >> 32) == 0;
@@ -1338,19 +1414,27 @@ DEVI void scan_heavy_chunk(const ScanParams &S, const uint64_t *key, uint64_t *p
         if (e < end) {
             const uint2 a = S.g.adj[e];
             const uint64_t ku = key[a.x];
+            n_ent++;
+            n_gat++;
             if (ku == KEY_INF) {
                 set_err(err, ERR_DIST_OVERFLOW);
             } else {
                 if (!is_seed && (uint32_t)ku == (uint32_t)kv && (ku >> 32) + a.y == (kv >> 32))
                     best = min(best, caller_id(S.g, a.x));
-                if (row < a.x) boundary_candidate(S.g, pt, tr, err, kv, ra, ku, a.y, e);
+                if (row < a.x) {
+                    const int c = boundary_candidate(S.g, pt, tr, err, kv, ra, ku, a.y, e);
+                    n_cand += c != 0;
+                    n_atom += c == 2;
+                }
             }
         }
     }
     best = wave_min(best);
     if (lane() == 0 && best != NONE) atomicMin(heavy_pe + h, best);
+    if (COUNT) scan_count(S.ev, n_ent, n_gat, n_cand, n_atom);
 }
 
+template <bool REV, bool COUNT>
 __global__ void __launch_bounds__(256) k_scan(ScanParams S) {
     __shared__ ScanWave s_wave[4];
     const uint32_t n = S.g.n;
@@ -1368,9 +1452,10 @@ __global__ void __launch_bounds__(256) k_scan(ScanParams S) {
         const uint32_t *tr = S.tr ? S.tr[slot] : nullptr;
         uint32_t *err = S.slot_err + slot;
         if (lu < ngroups)
-            scan_light_group(S, key, S.aux + (size_t)slot * n, pt, tr, err, lu, &s_wave[w]);
+            scan_light_group<REV, COUNT>(S, key, S.aux + (size_t)slot * n, pt, tr, err,
+                                         S.heavy_pe + (size_t)slot * S.g.nheavy, lu, &s_wave[w]);
         else
-            scan_heavy_chunk(S, key, pt, tr, err, S.heavy_pe + (size_t)slot * S.g.nheavy, lu - ngroups);
+            scan_heavy_chunk<REV, COUNT>(S, key, pt, tr, err, S.heavy_pe + (size_t)slot * S.g.nheavy, lu - ngroups);
     }
 }
 
@@ -2086,7 +2171,11 @@ hipError_t launch_persistent(const VorParams &P, uint32_t grid, uint32_t block, 
 }
 
 hipError_t launch_scan(const ScanParams &S, uint32_t grid, uint32_t block, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(grid), dim3(block), 0, s, S);
+    const bool rev = !S.with_pred && S.g.reverse_scan, cnt = S.ev != nullptr;
+    if (rev && cnt) hipLaunchKernelGGL((k_scan<true, true>), dim3(grid), dim3(block), 0, s, S);
+    else if (rev) hipLaunchKernelGGL((k_scan<true, false>), dim3(grid), dim3(block), 0, s, S);
+    else if (cnt) hipLaunchKernelGGL((k_scan<false, true>), dim3(grid), dim3(block), 0, s, S);
+    else hipLaunchKernelGGL((k_scan<false, false>), dim3(grid), dim3(block), 0, s, S);
     if (S.g.nheavy) {
         const uint64_t t = (uint64_t)S.g.nheavy * S.nscan;
         hipLaunchKernelGGL(k_scan_heavy_pred, dim3(fill_grid(t)), dim3(256), 0, s, S);

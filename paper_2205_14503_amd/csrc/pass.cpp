@@ -596,6 +596,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     SP.nscan = Q;
     SP.slot_err = (uint32_t *)(ctl + L.slot_err);
     SP.with_pred = o.lazy_pred ? 0 : 1;
+    SP.ev = o.counting ? P.cnt->scan_ev : nullptr;
     for (uint32_t a : act)
         if (qs[a].want_key) SP.with_pred = 1;
     const uint32_t sgrid = (uint32_t)std::max(1, g->cu_count) * 8;
@@ -718,6 +719,10 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         x.pushes_next = hcnt.ev[EV_GLOBAL];
         x.parked = hcnt.ev[EV_PARK];
         x.items = hcnt.ev[EV_ITEMS];
+        x.scan_entries = hcnt.scan_ev[SCAN_EV_ENTRIES];
+        x.scan_gathers = hcnt.scan_ev[SCAN_EV_GATHERS];
+        x.scan_candidates = hcnt.scan_ev[SCAN_EV_CANDIDATES];
+        x.scan_atomics = hcnt.scan_ev[SCAN_EV_ATOMICS];
     }
     return STEINER_OK;
 }

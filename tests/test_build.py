@@ -1,6 +1,7 @@
-"""Compile-time properties of the relaxation kernel (no GPU needed): its
-in-flight loads and atomics must stay in registers (no scratch spills) at
-four or more waves per SIMD."""
+"""Compile-time properties of the relaxation and boundary-scan kernels (no
+GPU needed): the relaxation's in-flight loads and atomics must stay in
+registers (no scratch spills) at four or more waves per SIMD, and the scan
+(bound by its memory traffic) keeps eight waves per SIMD."""
 import os
 import re
 import subprocess
@@ -29,5 +30,9 @@ def test_round_kernel_occupancy(tmp_path):
     for rnd in rounds:
         assert int(rnd["Occupancy [waves/SIMD]"]) >= 4, rnd
         assert int(rnd["ScratchSize [bytes/lane]"]) == 0, rnd
-    scan = next(v for k, v in info.items() if k.startswith("_ZN3stn6k_scan"))
-    assert int(scan["Occupancy [waves/SIMD]"]) >= 8, scan
+    # the boundary scan's instances without event counters (forward and reversed edge direction)
+    scans = [v for k, v in info.items() if k.startswith("_ZN3stn6k_scan") and k.endswith("ELb0EEEvNS_10ScanParamsE")]
+    assert len(scans) == 2, list(info)
+    for scan in scans:
+        assert int(scan["Occupancy [waves/SIMD]"]) >= 8, scan
+        assert int(scan["ScratchSize [bytes/lane]"]) == 0, scan
