@@ -222,16 +222,17 @@ def bench_batch(args, st, W, np, torch, stream):
     dg = st.Graph(g, 0, stream)
     if not args.no_tune:
         dg.tune(sets[len(sets) // 2])
+    bopts = {"driver": args.driver} if args.driver else None
     for _ in range(args.warmup):
-        dg.solve_batch(sets)
+        dg.solve_batch(sets, bopts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        batch = dg.solve_batch(sets)
+        batch = dg.solve_batch(sets, bopts)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / args.steps
     t0 = time.perf_counter()
-    single = [dg.solve(s) for s in sets]
+    single = [dg.solve(s, bopts) for s in sets]
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     assert all(code == st.OK and tr.edges == sg.edges for (code, tr), sg in zip(batch, single)), \
@@ -269,7 +270,7 @@ def bench_serve(args, st, W, np, torch, stream):
     for rho in (0.5, 0.9, 1.5):
         rate = rho * mu
         arrivals = W.poisson_arrivals(nq, rate, master=7)
-        srv = st.steiner_server_create(dg.handle, budget, args.slots)
+        srv = st.steiner_server_create(dg.handle, budget, args.slots, {"driver": args.driver} if args.driver else None)
         tickets = [None] * nq
         lat = [0.0] * nq
         done = [None] * nq

@@ -69,7 +69,9 @@ typedef struct steiner_options {
     uint32_t delta;       /* bucket width of the distance-ordered relaxation; 0 = default for the graph,
                              0xFFFFFFFF = one unbounded bucket (plain label correcting) */
     uint32_t driver;      /* 0 = default, 1 = host-stepped rounds, 2 = one persistent cooperative kernel,
-                             3 = cluster-local relaxation in LDS (single queries; batches use 1) */
+                             3 = cluster-local relaxation in LDS (single queries; batches use 1),
+                             4 = host-stepped rounds replayed as HIP graphs of 8 launches (built once per
+                             graph and pass shape; the server replays its 4-round chunks) */
     uint32_t block;       /* threads per workgroup (multiple of 64, <= 1024); 0 = default */
     uint32_t grid;        /* workgroups of the relaxation pass; 0 = default */
     uint32_t small_max;   /* rows up to this degree are expanded wave-cooperatively; 0 = default */

@@ -60,11 +60,25 @@ struct TailScratch {
     void release();
 };
 
+// An instantiated graph of consecutive round-kernel launches (the graph-captured driver), rebuilt when the
+// pass parameters, launch shape or length change.
+struct RoundGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint8_t> key;  // VorParams bytes, grid, block, rounds
+    int get(const VorParams &P, uint32_t grid, uint32_t block, uint32_t rounds, hipGraphExec_t *out);
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        key.clear();
+    }
+};
+
 // Device workspace of a multi-query pass, reused across solves of a graph.
 struct Workspace {
     DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, seeds, pt, cidx, cval, ptrs;
     HostPinned host;
     TailScratch tail;
+    RoundGraph rgraph;
     std::vector<hipEvent_t> events;  // timing mode: reused event pool
     void release() {
         DevBuf *all[] = {&key, &aux, &dirty, &settled, &items_s[0], &items_s[1], &items_b[0], &items_b[1], &ctl, &heavy_pe,
@@ -72,10 +86,13 @@ struct Workspace {
         for (DevBuf *b : all) b->release();
         host.release();
         tail.release();
+        rgraph.release();
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         events.clear();
     }
 };
+// Rounds per launch of the graph-captured driver.
+constexpr uint32_t GRAPH_ROUNDS = 8;
 
 enum StopAfter { STOP_NEVER = 0, STOP_AFTER_SCAN = 1, STOP_AFTER_COMPACT = 2 };
 

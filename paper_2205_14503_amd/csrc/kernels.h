@@ -60,6 +60,10 @@ hipError_t launch_slot_start(const VorParams &P, uint32_t slot, const uint32_t *
                              uint32_t *heavy_pe_slot, uint32_t nheavy, hipStream_t s);
 // One round of the host-stepped driver: relax + control + advance scan.
 hipError_t launch_round(const VorParams &P, uint32_t grid, uint32_t block, hipStream_t s);
+// A HIP graph of `rounds` consecutive round-kernel launches with parameters P
+// (the graph-captured driver): launched as one unit, it replaces a chunk of
+// host launches; rounds after convergence exit at once.
+hipError_t build_round_graph(const VorParams &P, uint32_t grid, uint32_t block, uint32_t rounds, hipGraphExec_t *exec);
 // The persistent driver: rounds until convergence or `max_rounds` rounds.
 hipError_t launch_persistent(const VorParams &P, uint32_t grid, uint32_t block, uint32_t max_rounds,
                              hipStream_t s);

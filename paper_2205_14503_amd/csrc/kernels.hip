@@ -2126,6 +2126,33 @@ hipError_t launch_round(const VorParams &P, uint32_t grid, uint32_t block, hipSt
     return hipGetLastError();
 }
 
+hipError_t build_round_graph(const VorParams &P, uint32_t grid, uint32_t block, uint32_t rounds, hipGraphExec_t *exec) {
+    *exec = nullptr;
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipGraphCreate(&gr, 0);
+    if (e != hipSuccess) return e;
+    const bool narrow = P.g.ell && P.g.max_deg <= min(ELL_W, P.small_max);
+    VorParams arg = P;
+    void *args[] = {(void *)&arg};
+    hipKernelNodeParams kp{};
+    kp.func = narrow ? (void *)k_round<true> : (void *)k_round<false>;
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(block);
+    kp.sharedMemBytes = (unsigned)wave_smem(block);
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t prev = nullptr;
+    for (uint32_t i = 0; i < rounds && e == hipSuccess; i++) {  // a chain: round i + 1 after round i
+        hipGraphNode_t node = nullptr;
+        e = hipGraphAddKernelNode(&node, gr, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        prev = node;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) *exec = nullptr;
+    return e;
+}
+
 hipError_t launch_cluster_start(const ClusterParams &C, const uint32_t *seeds, uint32_t k, hipStream_t s) {
     hipLaunchKernelGGL(k_cluster_start, dim3((k + 255) / 256 + 1), dim3(256), 0, s, C, seeds, k);
     return hipGetLastError();

@@ -164,6 +164,21 @@ int ClusterSet::build(steiner_graph *g) {
     return STEINER_OK;
 }
 
+int RoundGraph::get(const VorParams &P, uint32_t grid, uint32_t block, uint32_t rounds, hipGraphExec_t *out) {
+    std::vector<uint8_t> want(sizeof(VorParams) + 12);
+    memcpy(want.data(), &P, sizeof(VorParams));
+    const uint32_t shape[3] = {grid, block, rounds};
+    memcpy(want.data() + sizeof(VorParams), shape, 12);
+    if (!exec || want != key) {
+        release();
+        int rc = hip_check(build_round_graph(P, grid, block, rounds, &exec), "round graph");
+        if (rc) return rc;
+        key.swap(want);
+    }
+    *out = exec;
+    return STEINER_OK;
+}
+
 size_t mst_scratch_bytes(uint32_t k, uint64_t m) {
     const size_t k4 = ((size_t)k * 4 + 255) & ~(size_t)255, m4 = ((size_t)m * 4 + 255) & ~(size_t)255;
     return 256 + 5 * k4 + 2 * m4;
@@ -554,12 +569,25 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         uint32_t next_chunk = 4;
         // a batch's frontier is larger: at least half the resident workgroups
         const uint32_t grid = Q == 1 ? o.grid_tuned : std::max(o.grid_tuned, o.grid / 2);
+        // graph-captured driver: the chunk is whole replays of one graph of GRAPH_ROUNDS launches
+        hipGraphExec_t gexec = nullptr;
+        if (o.driver == 4 && (rc = ws.rgraph.get(P, grid, o.block, GRAPH_ROUNDS, &gexec))) return rc;
         for (;;) {
             kmark();
-            for (uint32_t i = 0; i < chunk_rounds; i++) {
-                rc = hip_check(launch_round(P, grid, o.block, st), "round");
-                relax_launches++;
-                if (rc) return rc;
+            if (gexec) {
+                const uint32_t reps = (chunk_rounds + GRAPH_ROUNDS - 1) / GRAPH_ROUNDS;
+                for (uint32_t i = 0; i < reps; i++) {
+                    rc = hip_check(hipGraphLaunch(gexec, st), "round graph launch");
+                    relax_launches += GRAPH_ROUNDS;
+                    if (rc) return rc;
+                }
+                chunk_rounds = reps * GRAPH_ROUNDS;
+            } else {
+                for (uint32_t i = 0; i < chunk_rounds; i++) {
+                    rc = hip_check(launch_round(P, grid, o.block, st), "round");
+                    relax_launches++;
+                    if (rc) return rc;
+                }
             }
             kmark();
             launched += chunk_rounds;

@@ -108,6 +108,7 @@ struct steiner_server {
     hipStream_t s_main = nullptr, s_tail = nullptr;
     DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, pool;
     TailScratch tail;
+    RoundGraph rgraph;  // the graph-captured driver's chunk of rounds
     HostPinned hbuf;
     Layout L{1};
     VorParams P{};
@@ -153,6 +154,7 @@ struct steiner_server {
         for (DevBuf *b : bufs) b->release();
         hbuf.release();
         tail.release();
+        rgraph.release();
         if (s_main) (void)hipStreamDestroy(s_main);
         if (s_tail) (void)hipStreamDestroy(s_tail);
         s_main = s_tail = nullptr;
@@ -250,8 +252,14 @@ void steiner_server::run_sched() {
         }
         lk.unlock();
         int rc = STEINER_OK;
-        for (uint32_t i = 0; i < rounds_per_chunk && !rc; i++)
-            rc = hip_check(launch_round(P, o.grid, o.block, s_main), "round");
+        if (o.driver == 4) {  // the chunk as one captured graph
+            hipGraphExec_t ge = nullptr;
+            rc = rgraph.get(P, o.grid, o.block, rounds_per_chunk, &ge);
+            if (!rc) rc = hip_check(hipGraphLaunch(ge, s_main), "round graph launch");
+        } else {
+            for (uint32_t i = 0; i < rounds_per_chunk && !rc; i++)
+                rc = hip_check(launch_round(P, o.grid, o.block, s_main), "round");
+        }
         if (!rc)
             rc = hip_check(hipMemcpyAsync(hc + L.pass, P.pass, sizeof(PassCtl), hipMemcpyDeviceToHost, s_main), "D2H pass");
         if (!rc)
@@ -386,7 +394,7 @@ extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes
     } cleanup{s};
     s->g = g;
     s->o = resolve_options(g, opt);
-    s->o.driver = 1;
+    if (s->o.driver != 4) s->o.driver = 1;  // host-stepped chunks (or their captured graphs)
     s->o.timing = false;
     s->o.counting = false;
     const uint32_t n = g->n;

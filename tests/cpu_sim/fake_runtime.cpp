@@ -85,6 +85,16 @@ hipError_t hipGetSymbolAddress(void **p, const void *sym) {
 }
 const char *hipGetErrorString(hipError_t) { return "simulated"; }
 long hipsim_live_allocs() { return g_live_allocs.load(); }
+namespace stn {
+struct SimGraph;
+hipError_t sim_graph_launch(SimGraph *g, hipStream_t s);
+void sim_graph_free(SimGraph *g);
+}  // namespace stn
+hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s) { return stn::sim_graph_launch((stn::SimGraph *)e, s); }
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) {
+    stn::sim_graph_free((stn::SimGraph *)e);
+    return hipSuccess;
+}
 long hipsim_live_device_bytes() {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
     return g_live_dev_bytes;
@@ -169,6 +179,25 @@ hipError_t launch_round(const VorParams &P, uint32_t, uint32_t, hipStream_t) {
     if (!any) P.pass->all_done = 1;
     return hipSuccess;
 }
+
+struct SimGraph {
+    VorParams P;
+    uint32_t grid, block, rounds;
+};
+
+hipError_t build_round_graph(const VorParams &P, uint32_t grid, uint32_t block, uint32_t rounds, hipGraphExec_t *exec) {
+    *exec = (hipGraphExec_t) new SimGraph{P, grid, block, rounds};
+    return hipSuccess;
+}
+
+hipError_t sim_graph_launch(SimGraph *g, hipStream_t s) {
+    for (uint32_t i = 0; i < g->rounds; i++) {
+        const hipError_t e = launch_round(g->P, g->grid, g->block, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+void sim_graph_free(SimGraph *g) { delete g; }
 
 int persistent_max_grid(uint32_t) { return 0; }
 int round_max_grid(uint32_t) { return 0; }

@@ -36,6 +36,7 @@ typedef enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2
 typedef enum { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 } hipMemcpyKind;
 typedef struct ihipStream_t *hipStream_t;
 typedef struct ihipEvent_t *hipEvent_t;
+typedef struct ihipGraphExec_t *hipGraphExec_t;
 struct hipDeviceProp_t {
     int multiProcessorCount;
 };
@@ -86,4 +87,6 @@ hipError_t hipEventElapsedTime(float *, hipEvent_t, hipEvent_t);
 hipError_t hipEventDestroy(hipEvent_t);
 hipError_t hipGetLastError();
 hipError_t hipGetSymbolAddress(void **, const void *);
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t);
+hipError_t hipGraphExecDestroy(hipGraphExec_t);
 const char *hipGetErrorString(hipError_t);

@@ -327,6 +327,24 @@ int main() {
                                    &g3) == STEINER_EINVAL);
     }
 
+    // the graph-captured driver: same trees as the host-stepped one
+    {
+        steiner_options go{};
+        go.driver = 4;
+        const uint32_t sd[] = {3, 44, 20, 61};
+        steiner_result *r1 = nullptr, *r2 = nullptr;
+        for (int rep = 0; rep < 3; rep++) {
+            CHECK(steiner_solve(g, sd, 4, &go, &r1) == STEINER_OK);
+            CHECK(steiner_solve(g, sd, 4, nullptr, &r2) == STEINER_OK);
+            uint64_t m1 = 0, m2 = 0;
+            CHECK(steiner_result_edges(r1, &m1, nullptr, nullptr, nullptr) == STEINER_OK);
+            CHECK(steiner_result_edges(r2, &m2, nullptr, nullptr, nullptr) == STEINER_OK);
+            CHECK(m1 == m2 && steiner_result_total(r1) == steiner_result_total(r2));
+            steiner_result_free(r1);
+            steiner_result_free(r2);
+        }
+    }
+
     // batch through the pass driver
     std::vector<std::vector<uint32_t>> sets = {{1, 5, 9}, {7}, {2, 2, 30}, {0, 63, 10, 20, 40}};
     std::vector<const uint32_t *> ptrs;

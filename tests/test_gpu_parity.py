@@ -30,6 +30,8 @@ OPTION_SETS = {
     "eager": dict(flags=st.FLAG_EAGER_PRED),
     "split": dict(delta=50, flags=st.FLAG_SPLIT),
     "split_chunky": dict(delta=7, flags=st.FLAG_SPLIT, small_max=1, chunk=64, local_iters=0xFFFFFFFF),
+    "graph": dict(driver=4),
+    "graph_bucketed": dict(driver=4, delta=50, local_iters=2),
 }
 
 
@@ -336,3 +338,23 @@ def test_seed_strategies(stream):
         check_case(g, W.make_seeds(g, 40, master=9, cand=cand, strategy=strat), stream, None, f"rmat14 {strat}")
         say(f"grid 61x67 seeds={strat}")
         check_case(gg, W.make_seeds(gg, 25, master=9, strategy=strat), stream, None, f"grid {strat}")
+
+
+def test_graph_driver_replays(stream):
+    """The graph-captured driver replays one instantiated graph across
+    solves: with the program's own solves, batches and synchronisations in
+    between, every replayed solve equals the host-stepped one and the oracle."""
+    import torch
+    g = W.rmat(14, 16, wlo=1, whi=1000)
+    cand = W.lcc(g)
+    sets = [W.sample(cand, k, master=21, stream=700 + i) for i, k in enumerate([5, 300, 40, 1000, 2])]
+    refs = [O.solve(g, s) for s in sets]
+    with st.Graph(g, 0, stream) as dg:
+        for rep in range(3):
+            for s, ref in zip(sets, refs):
+                got = dg.solve(s, dict(driver=4))
+                assert got.edges == ref.edges and got.total == ref.total, f"replay {rep}"
+                assert dg.solve(s).edges == ref.edges
+            torch.cuda.synchronize()
+            batch = dg.solve_batch(sets, dict(driver=4))
+            assert [t.edges for _, t in batch] == [r.edges for r in refs]

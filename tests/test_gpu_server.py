@@ -40,6 +40,7 @@ SERVER_OPTIONS = {
     "split": dict(delta=50, flags=st.FLAG_SPLIT),
     "no_local_queue": dict(local_iters=0xFFFFFFFF),
     "split_chunky": dict(delta=7, flags=st.FLAG_SPLIT, small_max=1, chunk=64, local_iters=0xFFFFFFFF),
+    "graph": dict(driver=4),
 }
 
 
