@@ -80,8 +80,8 @@ def _pmc_per_kernel(path: str):
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
-def _config_key(delta, local, split=False, grid=0) -> str:
-    key = f"delta={int(delta)},local_iters={int(local)},split={int(bool(split))}"
+def _config_key(delta, local, split=None, grid=0) -> str:
+    key = f"delta={int(delta)},local_iters={int(local)},split={split or 0}"
     return key + (f",grid={int(grid)}" if grid else "")
 
 
@@ -108,7 +108,7 @@ def pmc_summary(args):
             lines.append(f"| {name} | {cnt} | {fv:.1f} | {wv:.1f} | {mb:.3f} |")
     entry["bytes_per_launch"] = entry["per_kernel"]["k_round"]["bytes"]
     data = json.load(open(TRAFFIC_FILE)) if os.path.exists(TRAFFIC_FILE) else {}
-    data.setdefault(args.workload, {})[_config_key(args.delta, args.local, False, args.grid)] = entry
+    data.setdefault(args.workload, {})[_config_key(args.delta, args.local, args.split, args.grid)] = entry
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
     print(f"Copy calibration: a 1 GiB device copy reads {copy_kib / f_scale:.1f} KiB of FETCH_SIZE "
@@ -249,7 +249,11 @@ def bench_batch(args, st, W, np, torch, stream):
 
 
 def bench_serve(args, st, W, np, torch, stream):
-    """Poisson arrivals into the continuous-batching server at rho x the sequential rate."""
+    """Poisson arrivals into the continuous-batching server at rho x the
+    sequential rate (rho = inf: every request submitted at once, which
+    measures the server's capacity).  The sequential rate is measured on the
+    same requests solved one at a time, and every served tree must equal the
+    same request's solve alone."""
     import threading
     spec = W.WORKLOADS[args.workload]
     g = W.make_graph(args.workload)
@@ -259,18 +263,22 @@ def bench_serve(args, st, W, np, torch, stream):
     dg = st.Graph(g, 0, stream)
     if not args.no_tune:
         dg.tune(sets[0])
-    ref = {}
+    sopts = {"driver": args.driver} if args.driver else None
+    for s in sets[:3]:
+        dg.solve(s, sopts)  # warm-up
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    nseq = min(nq, args.seq_sample)
-    for q in range(nseq):
-        ref[q] = dg.solve(sets[q])
-    mu = nseq / (time.perf_counter() - t0)
+    ref = [dg.solve(s, sopts).edges for s in sets]
+    mu = nq / (time.perf_counter() - t0)
+    print(f"[bench] serve: {nq} requests one at a time: {mu:.2f} queries/s", file=sys.stderr, flush=True)
     budget = args.budget_gb << 30
     out = {"rho": {}}
-    for rho in (0.5, 0.9, 1.5):
+    for rho_s in args.rhos.split(","):
+        rho = float(rho_s)
         rate = rho * mu
-        arrivals = W.poisson_arrivals(nq, rate, master=7)
-        srv = st.steiner_server_create(dg.handle, budget, args.slots, {"driver": args.driver} if args.driver else None)
+        arrivals = W.poisson_arrivals(nq, rate, master=7) if rho != float("inf") else np.zeros(nq)
+        srv = st.steiner_server_create(dg.handle, budget, args.slots, sopts)
+        mem = st.steiner_server_memory(srv)
         tickets = [None] * nq
         lat = [0.0] * nq
         done = [None] * nq
@@ -294,21 +302,26 @@ def bench_serve(args, st, W, np, torch, stream):
         th.join()
         wall = time.perf_counter() - start
         st.steiner_server_destroy(srv)
-        for q in ref:
-            assert done[q].edges == ref[q].edges, "served result differs from the result alone"
-        out["rho"][str(rho)] = {"offered_qps": round(rate, 2), "queries_per_s": round(nq / wall, 2),
-                                "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                                "p99_ms": round(float(np.percentile(lat, 99)), 3)}
-        print(f"[bench] serve rho={rho}: {out['rho'][str(rho)]}", file=sys.stderr, flush=True)
+        for q in range(nq):
+            assert done[q].edges == ref[q], f"served result {q} differs from the result alone"
+        key = "inf" if rho == float("inf") else str(rho)
+        out["rho"][key] = {"offered_qps": None if rho == float("inf") else round(rate, 2),
+                           "queries_per_s": round(nq / wall, 2),
+                           "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                           "slots": mem["slots"]}
+        print(f"[bench] serve rho={key}: {out['rho'][key]}", file=sys.stderr, flush=True)
     best = max(v["queries_per_s"] for v in out["rho"].values())
+    mid = out["rho"].get("0.9") or next(iter(out["rho"].values()))
     return {
         "metric": METRIC, "value": best, "unit": "queries/s", "n_gpus": 1, "steps": nq, "warmup": 0,
         "ms_per_step": round(1e3 / best, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "queries": nq, "slots": args.slots,
-                   "budget_gb": args.budget_gb, "seed": 1},
-        "sequential_queries_per_s": round(mu, 3), "serving": out,
-        "p50_ms": out["rho"]["0.9"]["p50_ms"], "p99_ms": out["rho"]["0.9"]["p99_ms"],
+                   "budget_gb": args.budget_gb, "seed": 1, "k_range": [spec["k_lo"], spec["k_hi"]]},
+        "sequential_queries_per_s": round(mu, 3), "served_over_sequential": round(best / mu, 3),
+        "serving": out, "p50_ms": mid["p50_ms"], "p99_ms": mid["p99_ms"],
+        "parity": f"all {nq} served trees equal the same requests solved alone, at every rate",
     }
 
 
@@ -323,12 +336,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--queries", type=int, default=300, help="serving: number of requests per rate")
-    ap.add_argument("--seq-sample", type=int, default=30, help="serving: queries solved alone to set the rate")
-    ap.add_argument("--slots", type=int, default=32, help="serving: resident query slots")
+    ap.add_argument("--queries", type=int, default=1000, help="serving: number of requests per rate")
+    ap.add_argument("--rhos", default="0.5,0.9,1.5,inf",
+                    help="serving: offered load as multiples of the sequential rate (inf: all at once)")
+    ap.add_argument("--slots", type=int, default=8, help="serving: resident query slots")
     ap.add_argument("--budget-gb", type=int, default=96, help="serving: device memory budget")
     ap.add_argument("--local", type=int, default=0, help="local-queue depth (with --delta: skips the tuner)")
     ap.add_argument("--grid", type=int, default=0, help="relaxation workgroups (with --delta: skips the tuner)")
+    ap.add_argument("--split", default=None, choices=["weight"],
+                    help="light/heavy edge split (with --delta: skips the tuner)")
     ap.add_argument("--seeds", default="uniform", help="seed strategy: uniform, bfs_level, eccentric, proximate")
     ap.add_argument("--sweep", action="store_true", help="run the sensitivity studies instead of the benchmark")
     ap.add_argument("--sweep-scale", type=int, default=22, help="RMAT scale of the sensitivity studies")
@@ -390,13 +406,16 @@ def main():
         opts["local_iters"] = args.local
     if args.grid:
         opts["grid"] = args.grid
+    if args.split:
+        opts["flags"] |= st.FLAG_SPLIT
     dg = st.Graph(g, 0, stream)
     tuned = None
     if not args.no_tune and not args.delta:
         t0 = time.time()
         tuned = dg.tune(seeds)  # set-up, like the upload: picks delta and the local-queue depth
+        split = "weight" if tuned["flags"] & st.FLAG_SPLIT else None
         tuned = {"delta": tuned["delta"], "local_iters": tuned["local_iters"], "grid": tuned["grid"],
-                 "split": bool(tuned["flags"] & st.FLAG_SPLIT), "lazy_pred": bool(tuned["flags"] & st.FLAG_LAZY_PRED),
+                 "split": split, "lazy_pred": bool(tuned["flags"] & st.FLAG_LAZY_PRED),
                  "seconds": round(time.time() - t0, 2)}
         print(f"[bench] tuned {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -435,7 +454,7 @@ def main():
         try:
             delta = opts.get("delta", tuned and tuned["delta"])
             local = opts.get("local_iters", tuned and tuned["local_iters"])
-            split = bool(tuned and tuned["split"])
+            split = args.split or (tuned and tuned["split"])
             grid = opts.get("grid", tuned["grid"] if tuned else 0)
             ent = json.load(open(TRAFFIC_FILE)).get(args.workload, {}).get(_config_key(delta, local, split, grid))
             if ent and ent.get("kernel_sha") == kernel_sha():

@@ -115,6 +115,9 @@ typedef struct steiner_stats {
      * read, neighbour keys gathered, cross-cell candidates (each reads its
      * pair's current entry), atomicMins issued on the pair table. */
     uint64_t scan_entries, scan_gathers, scan_candidates, scan_atomics;
+    /* With STEINER_FLAG_COUNTERS: the relaxation attempts made from chunks of
+     * rows above small_max (part of relax_attempts). */
+    uint64_t relax_attempts_large;
 } steiner_stats;
 
 /* Upload flags. */

@@ -66,7 +66,7 @@ class steiner_stats(ctypes.Structure):
         ("ms_init", "ms_voronoi", "ms_scan", "ms_compact", "ms_mst", "ms_expand", "ms_total", "ms_relax_kernels")] + [
         (name, ctypes.c_uint64) for name in
         ("relax_attempts", "relax_atomics", "relax_improved", "pushes_local", "pushes_next", "parked", "items",
-         "scan_entries", "scan_gathers", "scan_candidates", "scan_atomics")]
+         "scan_entries", "scan_gathers", "scan_candidates", "scan_atomics", "relax_attempts_large")]
 
 
 _lib = None

@@ -66,12 +66,12 @@ struct Counters {
     uint32_t grp_done[8 * 32];
     // event counters (only with counting enabled): relaxation attempts,
     // atomicMins issued, improvements, local-queue pushes, next-round pushes,
-    // parked vertices, items expanded
+    // parked vertices, items expanded, attempts from chunks of large rows
     unsigned long long ev[8];
     unsigned long long scan_ev[4];  // boundary-scan events (counting mode), see ScanParams::ev
 };
 constexpr uint32_t ROUND_GROUPS = 8;
-enum { EV_ATTEMPT = 0, EV_ATOMIC, EV_IMPROVED, EV_LOCAL, EV_GLOBAL, EV_PARK, EV_ITEMS, EV_N };
+enum { EV_ATTEMPT = 0, EV_ATOMIC, EV_IMPROVED, EV_LOCAL, EV_GLOBAL, EV_PARK, EV_ITEMS, EV_LARGE, EV_N };
 
 constexpr uint32_t ELL_W = 4;
 constexpr uint32_t ELL_NONE = 0xFFFFFFFFu;
@@ -136,6 +136,13 @@ struct VorParams {
     uint32_t counting;    // 1: accumulate Counters::ev
     uint32_t split;       // 1: light/heavy edge split (finite delta)
     uint32_t lq_mode;     // bit 0: drain the local queue smallest distance first; bit 1: skip superseded entries
+    // Chunk memory (null when off): the rows above small_max are the vertices below nxrow (a degree-renumbered
+    // graph) and chunk c of row v is chunk number xchunk[v] + c of xchunks per query; xkey[slot * xchunks + i]
+    // is the key chunk i was last expanded with (all ones: never).  A chunk whose row still holds that key
+    // has nothing new to push and is skipped.
+    uint64_t *xkey;
+    const uint32_t *xchunk;
+    uint32_t nxrow, xchunks;
 };
 
 enum : uint32_t {

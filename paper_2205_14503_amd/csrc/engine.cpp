@@ -716,6 +716,8 @@ extern "C" int steiner_graph_free(steiner_graph *g) {
     (void)hipStreamSynchronize(g->stream);
     g->ws.release();
     g->clusters.release();
+    for (auto &kv : g->chunk_tables)
+        if (kv.second) kv.second->start.release();
     dev_free(g->d_rp);
     dev_free(g->d_adj);
     dev_free(g->d_ell);

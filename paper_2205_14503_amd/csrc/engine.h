@@ -75,14 +75,14 @@ struct RoundGraph {
 
 // Device workspace of a multi-query pass, reused across solves of a graph.
 struct Workspace {
-    DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, seeds, pt, cidx, cval, ptrs;
+    DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, seeds, pt, cidx, cval, ptrs, xkey;
     HostPinned host;
     TailScratch tail;
     RoundGraph rgraph;
     std::vector<hipEvent_t> events;  // timing mode: reused event pool
     void release() {
         DevBuf *all[] = {&key, &aux, &dirty, &settled, &items_s[0], &items_s[1], &items_b[0], &items_b[1], &ctl, &heavy_pe,
-                         &seeds, &pt, &cidx, &cval, &ptrs};
+                         &seeds, &pt, &cidx, &cval, &ptrs, &xkey};
         for (DevBuf *b : all) b->release();
         host.release();
         tail.release();
@@ -150,6 +150,12 @@ struct steiner_result {
 };
 
 namespace stn {
+// Chunk numbering of the rows above small_max for the relaxation's chunk memory (VorParams::xkey): built
+// when those rows are the vertices below nxrow (a degree-renumbered graph).
+struct ChunkTable {
+    DevBuf start;  // [nxrow + 1] first chunk number of each row
+    uint32_t nxrow = 0, xchunks = 0;
+};
 // BFS-grown vertex clusters of the cluster-local driver (built on first use).
 struct ClusterSet {
     bool built = false;
@@ -197,6 +203,7 @@ struct steiner_graph {
     std::mutex mu;               // serialises solves on this graph
     mutable std::mutex memo_mu;  // guards chunk_memo
     mutable std::map<uint64_t, uint64_t> chunk_memo;  // (small_max << 32 | chunk) -> chunks of rows above small_max
+    std::map<uint64_t, std::unique_ptr<stn::ChunkTable>> chunk_tables;  // (small_max << 32 | chunk), guarded by mu
     stn::Workspace ws;
     stn::ClusterSet clusters;
 };
@@ -227,7 +234,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs);
 int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
                  const uint64_t *pt, const uint32_t *tr, const uint32_t *g1_idx, uint32_t m, bool pred_ready,
                  TailScratch &ts, uint8_t *mst_buf, std::unique_ptr<steiner_result> &out, double *ms_mst,
-                 double *ms_expand);
+                 double *ms_expand, uint32_t mst_block = 0);
 // Bytes of the MST's scratch for k seeds and a G'1 of m entries.
 size_t mst_scratch_bytes(uint32_t k, uint64_t m);
 // Device buffers of Steps 3-6 for one query: the MST's scratch (mst_scratch_bytes; its first 16 bytes
@@ -236,6 +243,7 @@ size_t mst_scratch_bytes(uint32_t k, uint64_t m);
 struct TreeBufs {
     uint8_t *mst;
     uint32_t *mark, *out;
+    uint32_t mst_block = 0;  // threads of the MST's single-workgroup kernels (0: 1024)
 };
 // Launches Steps 3-6 of one query on st (see tree_from_g1); ev_mid (optional) is recorded between the MST and
 // the expansion.
@@ -249,9 +257,15 @@ void seed_ranks(const steiner_graph *g, const std::vector<uint32_t> &S, std::vec
 void pair_from_index(uint64_t p, uint32_t *i, uint32_t *j);
 int canon_seeds(const steiner_graph *g, const uint32_t *seeds, uint32_t k, std::vector<uint32_t> &S);
 uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chunk, bool remember = true);
+// The chunk numbering for (small_max, chunk), built once per graph; null when the rows above small_max are
+// not a prefix of the vertex ids (then the relaxation runs without chunk memory).  Caller holds g->mu.
+const ChunkTable *chunk_table(steiner_graph *g, uint32_t small_max, uint32_t chunk, int *rc);
 // Looks up the allocation-free solve's device scratch on `device` (the current device) once per device.
 void noalloc_setup(int device);
 // Fills the pass parameters shared by every driver for Q slots.
 void bind_state(VorParams &P, const Options &o, uint64_t cap_s, uint64_t cap_b);
+// After bind_state: the large rows' chunk memory for Q slots in `xkey` (allocated here; a DevBuf with enough
+// room already is reused), where the graph allows it.  Caller holds g->mu.
+int bind_chunk_memory(VorParams &P, steiner_graph *g, const Options &o, uint32_t Q, DevBuf &xkey);
 
 }  // namespace stn

@@ -90,6 +90,7 @@ struct MstParams {
     uint32_t *hook;           // [k] parent of each root after the current round's hooking
     unsigned long long *best; // [k] lightest key leaving each root
     uint32_t *sel;            // [k] chosen cross-cell edge ids (caller CSR offsets), hdr[2] of them
+    uint32_t block;           // threads of the single-workgroup steps (1024; 256 fits beside a running pass)
 };
 hipError_t launch_mst(const MstParams &M, const uint32_t *g1_idx, uint32_t m, hipStream_t s);
 

@@ -359,6 +359,12 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
     const uint32_t c = (uint32_t)(it >> 32) & ((1u << CHUNK_BITS) - 1);
     const uint32_t v = (uint32_t)it;
     const uint64_t kv = ld_agent(P.key + (size_t)slot * P.g.n + v);
+    bool again = false;  // this chunk was already expanded with this very key: nothing new to push
+    if (P.xkey && v < P.nxrow && kv != KEY_INF) {
+        uint64_t *xk = P.xkey + (size_t)slot * P.xchunks + P.xchunk[v] + c;
+        again = *xk == kv;
+        if (!again && lane() == 0) *xk = kv;
+    }
     if (P.split && !heavy && c == 0 && kv != KEY_INF) {  // heavy edges wait until the bucket closes
         if (lane() == 0) {
             P.settled[(size_t)slot * P.g.n + v] = 1;
@@ -369,7 +375,7 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
     const uint32_t beg = P.g.rp[v] + c * P.chunk;
     const uint32_t lim = P.g.rp[v + 1];
     uint32_t end = (lim - beg > P.chunk) ? beg + P.chunk : lim;
-    if (kv == KEY_INF) end = beg;
+    if (kv == KEY_INF || again) end = beg;
     for (uint32_t e0 = beg; e0 < end; e0 += 64 * UNROLL) {
         bool valid[UNROLL];
         uint32_t sl[UNROLL], uu[UNROLL], ww[UNROLL];
@@ -384,6 +390,7 @@ DEVI void process_b_chunk(const VorParams &P, const RoundIdx &R, const uint64_t 
             if (P.split) valid[i] = valid[i] && (heavy ? a.y > P.delta : a.y <= P.delta);
             sl[i] = slot;
             ks[i] = kv;
+            count(P, L, EV_LARGE, valid[i]);
         }
         relax_multi(P, R, thr, valid, sl, ks, uu, ww, L, use_lq, lq_head, lq_tail);
     }
@@ -2111,6 +2118,9 @@ hipError_t launch_slot_start(const VorParams &P, uint32_t slot, const uint32_t *
     hipLaunchKernelGGL(k_slot_clear, dim3(fill_grid(n)), dim3(256), 0, s, P.key + (size_t)slot * n,
                        P.aux + (size_t)slot * n, P.dirty + (size_t)slot * n, P.settled + (size_t)slot * n, n,
                        heavy_pe_slot, nheavy);
+    if (P.xkey)
+        hipLaunchKernelGGL(k_fill<uint64_t>, dim3(fill_grid(P.xchunks)), dim3(256), 0, s,
+                           P.xkey + (size_t)slot * P.xchunks, (uint64_t)P.xchunks, KEY_INF);
     hipLaunchKernelGGL(k_slot_seed, dim3(1), dim3(256), 0, s, P, slot, d_seeds, k);
     return hipGetLastError();
 }
@@ -2231,8 +2241,9 @@ hipError_t launch_mst(const MstParams &M, const uint32_t *g1_idx, uint32_t m, hi
     // every round at least halves the number of components that still have an outgoing edge
     uint32_t rounds = 1;
     while ((1ull << rounds) < M.k) rounds++;
+    const uint32_t one = M.block ? M.block : 1024;  // workgroup size of the single-workgroup kernels
     if (m <= (1u << 16)) {
-        hipLaunchKernelGGL(k_mst_small, dim3(1), dim3(1024), 0, s, M, g1_idx, m, rounds);
+        hipLaunchKernelGGL(k_mst_small, dim3(1), dim3(one), 0, s, M, g1_idx, m, rounds);
         return hipGetLastError();
     }
     const uint32_t grid = (uint32_t)std::min<uint64_t>(2048, ((uint64_t)std::max(m, M.k) + 255) / 256);
@@ -2240,7 +2251,7 @@ hipError_t launch_mst(const MstParams &M, const uint32_t *g1_idx, uint32_t m, hi
     const uint32_t egrid = (uint32_t)std::min<uint64_t>(2048, ((uint64_t)m + 255) / 256 + 1);
     for (uint32_t r = 0; r <= rounds; r++) {
         hipLaunchKernelGGL(k_mst_edges, dim3(egrid), dim3(256), 0, s, M, r & 1u);
-        hipLaunchKernelGGL(k_mst_merge, dim3(1), dim3(1024), 0, s, M, r & 1u);
+        hipLaunchKernelGGL(k_mst_merge, dim3(1), dim3(one), 0, s, M, r & 1u);
     }
     return hipGetLastError();
 }

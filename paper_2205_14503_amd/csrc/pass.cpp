@@ -29,6 +29,61 @@ uint64_t big_row_chunks(const steiner_graph *g, uint32_t small_max, uint32_t chu
     return t;
 }
 
+const ChunkTable *chunk_table(steiner_graph *g, uint32_t small_max, uint32_t chunk, int *rc) {
+    *rc = STEINER_OK;
+    const uint64_t memo_key = ((uint64_t)small_max << 32) | chunk;
+    auto it = g->chunk_tables.find(memo_key);
+    if (it != g->chunk_tables.end()) return it->second.get();
+    std::unique_ptr<ChunkTable> t(new ChunkTable());
+    const uint32_t n = g->n;
+    uint32_t nx = 0;
+    while (nx < n && g->h_rp[nx + 1] - g->h_rp[nx] > small_max) nx++;
+    bool prefix = true;
+    for (uint32_t v = nx; v < n && prefix; v++) prefix = g->h_rp[v + 1] - g->h_rp[v] <= small_max;
+    if (!prefix || nx == 0) {
+        g->chunk_tables[memo_key] = nullptr;  // remembered: no chunk memory on this graph
+        return nullptr;
+    }
+    std::vector<uint32_t> start(nx + 1, 0);
+    uint64_t total = 0;
+    for (uint32_t v = 0; v < nx; v++) {
+        start[v] = (uint32_t)total;
+        total += (g->h_rp[v + 1] - g->h_rp[v] + chunk - 1) / chunk;
+    }
+    if (total >= (1ull << 32)) {
+        g->chunk_tables[memo_key] = nullptr;
+        return nullptr;
+    }
+    start[nx] = (uint32_t)total;
+    if ((*rc = t->start.ensure(((size_t)nx + 1) * 4))) return nullptr;
+    *rc = hip_check(hipMemcpyAsync(t->start.ptr, start.data(), ((size_t)nx + 1) * 4, hipMemcpyHostToDevice, g->stream),
+                    "H2D chunk table");
+    if (!*rc) *rc = hip_check(hipStreamSynchronize(g->stream), "chunk table");
+    if (*rc) {
+        t->start.release();
+        return nullptr;
+    }
+    t->nxrow = nx;
+    t->xchunks = (uint32_t)total;
+    ChunkTable *raw = t.get();
+    g->chunk_tables[memo_key] = std::move(t);
+    return raw;
+}
+
+int bind_chunk_memory(VorParams &P, steiner_graph *g, const Options &o, uint32_t Q, DevBuf &xkey) {
+    // The large rows' chunk memory: not with the light/heavy split, where a chunk is expanded once per edge
+    // class, and only when the rows above small_max are a prefix of the ids.
+    int rc = STEINER_OK;
+    const ChunkTable *ct = P.split ? nullptr : chunk_table(g, o.small_max, o.chunk, &rc);
+    if (rc || !ct) return rc;
+    if ((rc = xkey.ensure((size_t)Q * ct->xchunks * 8))) return rc;
+    P.xkey = xkey.as<uint64_t>();
+    P.xchunk = ct->start.as<uint32_t>();
+    P.nxrow = ct->nxrow;
+    P.xchunks = ct->xchunks;
+    return STEINER_OK;
+}
+
 void bind_pass(VorParams &P, const DevGraph &dg, uint8_t *ctl, const Layout &L, uint32_t Q) {
     P.g = dg;
     P.cnt = (Counters *)(ctl + L.counters);
@@ -230,6 +285,7 @@ int launch_tree(const steiner_graph *g, hipStream_t st, const uint64_t *key, uin
     M.best = (unsigned long long *)(base + 256 + 3 * k4);
     M.edges[0] = (uint32_t *)(base + 256 + 5 * k4);
     M.edges[1] = (uint32_t *)(base + 256 + 5 * k4 + m4);
+    M.block = tb.mst_block;
     ExpandParams EP{};
     EP.g = g->dg;
     EP.key = key;
@@ -255,11 +311,11 @@ int launch_tree(const steiner_graph *g, hipStream_t st, const uint64_t *key, uin
 int tree_from_g1(steiner_graph *g, hipStream_t st, const uint64_t *key, uint32_t *pred, uint32_t k,
                  const uint64_t *pt, const uint32_t *tr, const uint32_t *g1_idx, uint32_t m, bool pred_ready,
                  TailScratch &ts, uint8_t *mst_buf, std::unique_ptr<steiner_result> &out, double *ms_mst,
-                 double *ms_expand) {
+                 double *ms_expand, uint32_t mst_block) {
     const uint32_t n = g->n;
     int rc;
     if ((rc = ts.prepare(n, k, m, mst_buf == nullptr, st))) return rc;
-    TreeBufs tb{mst_buf ? mst_buf : ts.mst.as<uint8_t>(), ts.mark.as<uint32_t>(), ts.out.as<uint32_t>()};
+    TreeBufs tb{mst_buf ? mst_buf : ts.mst.as<uint8_t>(), ts.mark.as<uint32_t>(), ts.out.as<uint32_t>(), mst_block};
     const uint32_t *hdr = (const uint32_t *)tb.mst;
     const bool timed = ms_mst || ms_expand;
     rc = timed ? hip_check(hipEventRecord(ts.ev[0], st), "event") : STEINER_OK;
@@ -402,6 +458,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
     P.items_b[0] = ws.items_b[0].as<uint64_t>();
     P.items_b[1] = ws.items_b[1].as<uint64_t>();
     bind_state(P, o, cap_s, cap_b);
+    if ((rc = bind_chunk_memory(P, g, o, Q, ws.xkey))) return rc;
 
     // Per-slot pointer tables (host image, then one copy).
     {
@@ -747,6 +804,7 @@ int run_pass(steiner_graph *g, const Options &o, std::vector<Query> &qs) {
         x.pushes_next = hcnt.ev[EV_GLOBAL];
         x.parked = hcnt.ev[EV_PARK];
         x.items = hcnt.ev[EV_ITEMS];
+        x.relax_attempts_large = hcnt.ev[EV_LARGE];
         x.scan_entries = hcnt.scan_ev[SCAN_EV_ENTRIES];
         x.scan_gathers = hcnt.scan_ev[SCAN_EV_GATHERS];
         x.scan_candidates = hcnt.scan_ev[SCAN_EV_CANDIDATES];

@@ -106,7 +106,7 @@ struct steiner_server {
     uint64_t budget = 0, fixed_bytes = 0, slot_bytes = 0, pool_bytes = 0, used = 0;
     uint32_t S = 0;  // slots
     hipStream_t s_main = nullptr, s_tail = nullptr;
-    DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, pool;
+    DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, pool, xkey;
     TailScratch tail;
     RoundGraph rgraph;  // the graph-captured driver's chunk of rounds
     HostPinned hbuf;
@@ -150,7 +150,7 @@ struct steiner_server {
     int admit(Request *r, int slot);
     void free_device() {
         DevBuf *bufs[] = {&key, &aux, &dirty, &settled, &items_s[0], &items_s[1], &items_b[0], &items_b[1], &ctl,
-                          &heavy_pe, &pool};
+                          &heavy_pe, &pool, &xkey};
         for (DevBuf *b : bufs) b->release();
         hbuf.release();
         tail.release();
@@ -341,7 +341,7 @@ void steiner_server::run_tail() {
                 } else {
                     status = tree_from_g1(g, s_tail, P.key + (size_t)slot * n, P.aux + (size_t)slot * n, k,
                                           (const uint64_t *)region(r, 0), tr, oi, cnt, SP.with_pred != 0, tail,
-                                          region(r, 2), res, nullptr, nullptr);
+                                          region(r, 2), res, nullptr, nullptr, 256);
                 }
                 if (!status) res->stats.pairs = cnt;
             }
@@ -395,13 +395,24 @@ extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes
     s->g = g;
     s->o = resolve_options(g, opt);
     if (s->o.driver != 4) s->o.driver = 1;  // host-stepped chunks (or their captured graphs)
+    // the relaxation leaves a few workgroup slots free, so the tails' kernels (second stream) start at once
+    // instead of waiting for a gap between round kernels
+    if (!(opt && opt->grid)) s->o.grid = std::max<uint32_t>(1, s->o.grid - s->o.grid / 32);
     s->o.timing = false;
     s->o.counting = false;
     const uint32_t n = g->n;
     const uint64_t chunks = big_row_chunks(g, s->o.small_max, s->o.chunk);
-    // per slot: key 8 + stamp/pred 4 + park 1 + settled 1 bytes per vertex, the heavy rows' pred minima, and the
-    // slot's share of the two S lists (two entries of 8 bytes per vertex each) and of the two B lists
-    s->slot_bytes = 14ull * n + 4ull * g->nheavy + 32ull * n + 32ull * chunks;
+    const ChunkTable *ct = nullptr;  // chunk memory of the large rows (not with the light/heavy split)
+    if (!s->o.split || s->o.delta == 0xFFFFFFFFu) {
+        std::lock_guard<std::mutex> lk(g->mu);
+        ct = chunk_table(g, s->o.small_max, s->o.chunk, &rc);
+        if (rc) return rc;
+    }
+    const uint64_t xchunks = ct ? ct->xchunks : 0;
+    // per slot: key 8 + stamp/pred 4 + park 1 + settled 1 bytes per vertex, the heavy rows' pred minima, the
+    // slot's share of the two S lists (two entries of 8 bytes per vertex each) and of the two B lists, and the
+    // large rows' chunk memory
+    s->slot_bytes = 14ull * n + 4ull * g->nheavy + 32ull * n + 32ull * chunks + 8ull * xchunks;
     s->half = g->nnz / 2 + 1;
     const uint64_t mark_bytes = ((uint64_t)n + 3) / 4 * 4, out_bytes = 12ull * n + 16;
     s->fixed_bytes = steiner_server::al(Layout(max_slots).total) + steiner_server::al(mark_bytes) +
@@ -425,7 +436,8 @@ extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes
         (rc = s->items_b[0].ensure(cap_b * 8, true)) || (rc = s->items_b[1].ensure(cap_b * 8, true)) ||
         (rc = s->ctl.ensure(s->L.total, true)) || (rc = s->heavy_pe.ensure((size_t)S * g->nheavy * 4 + 4, true)) ||
         (rc = s->tail.mark.ensure(mark_bytes, true)) || (rc = s->tail.out.ensure(out_bytes, true)) ||
-        (rc = s->pool.ensure(s->pool_bytes, true)) || (rc = s->hbuf.ensure(s->L.total + 4096)))
+        (rc = s->pool.ensure(s->pool_bytes, true)) || (rc = s->hbuf.ensure(s->L.total + 4096)) ||
+        (xchunks && (rc = s->xkey.ensure((size_t)S * xchunks * 8, true))))
         return rc;
     s->pa.init(s->pool_bytes);
     if ((rc = hip_check(hipStreamCreateWithFlags(&s->s_main, hipStreamNonBlocking), "stream"))) return rc;
@@ -441,6 +453,10 @@ extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes
     P.items_b[0] = s->items_b[0].as<uint64_t>();
     P.items_b[1] = s->items_b[1].as<uint64_t>();
     bind_state(P, s->o, cap_s, cap_b);
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if ((rc = bind_chunk_memory(P, g, s->o, S, s->xkey))) return rc;  // the exact buffer made above
+    }
     if ((rc = hip_check(launch_pass_reset(P, s->s_main), "pass reset"))) return rc;
     if ((rc = hip_check(launch_fill_u32(s->tail.mark.as<uint32_t>(), mark_bytes / 4, 0u, s->s_main), "mark clear")))
         return rc;

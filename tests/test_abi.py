@@ -53,4 +53,4 @@ def test_null_arguments_rejected_without_gpu():
 
 def test_options_struct_layout():
     assert ctypes.sizeof(st.steiner_options) == 32
-    assert ctypes.sizeof(st.steiner_stats) == 24 + 8 * 8 + 11 * 8
+    assert ctypes.sizeof(st.steiner_stats) == 24 + 8 * 8 + 12 * 8
