@@ -884,7 +884,13 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
         (int)min(cur == 0 ? b3[0] : cur == 1 ? b3[1] : b3[2], P.cap_b));
     const RoundIdx R = round_idx((uint32_t)__builtin_amdgcn_readfirstlane((int)r));
     const uint32_t wpb = blockDim.x / 64, w = threadIdx.x / 64;
-    const uint32_t wave_gid = blockIdx.x * wpb + w, nwaves = gridDim.x * wpb;
+    // Workgroups that take part in this round: all of them when parked vertices move (the advance scans every
+    // vertex), else as many as the round's units need (one unit per wave).  The others leave at once and are not
+    // counted, so a large grid costs little in rounds with a small frontier.
+    const uint32_t units = (cs + 63) / 64 + cb;
+    const uint32_t part = any_adv ? gridDim.x : max(1u, min(gridDim.x, (units + wpb - 1) / wpb));
+    if (blockIdx.x >= part) return;
+    const uint32_t wave_gid = blockIdx.x * wpb + w, nwaves = part * wpb;
     if (any_adv)
         advance_body(P, P.slot.thr, P.slot.thr_prev, P.slot.adv, R.r + 1, R.nxt, R.c_nxt, R.b, (int)R.b, wave_gid,
                      nwaves, &s_wave[w]);
@@ -893,8 +899,8 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
     __syncthreads();
     if (threadIdx.x == 0) {  // the last workgroup of its group, then the last group, takes the decision
         __threadfence();
-        const uint32_t ng = min(gridDim.x, ROUND_GROUPS), grp = blockIdx.x % ng;
-        const uint32_t gsize = (gridDim.x - grp + ng - 1) / ng;  // workgroups with this residue
+        const uint32_t ng = min(part, ROUND_GROUPS), grp = blockIdx.x % ng;
+        const uint32_t gsize = (part - grp + ng - 1) / ng;  // workgroups with this residue
         uint32_t *gc = P.cnt->grp_done + grp * 32;
         s_last = 0;
         if (atomicAdd(gc, 1u) == gsize - 1) {
