@@ -291,6 +291,9 @@ def bench_serve(args, st, W, np, torch, stream):
                 tr = st.steiner_server_wait(srv, tickets[q])
                 lat[q] = tr.stats["ms_total"]
                 done[q] = tr
+                if (q + 1) % 100 == 0:
+                    print(f"[bench] serve rho={rho_s}: {q + 1} of {nq} done after {time.perf_counter() - start:.1f} s",
+                          file=sys.stderr, flush=True)
 
         th = threading.Thread(target=waiter)
         th.start()

@@ -47,7 +47,8 @@ struct PassCtl {
     uint32_t any_adv;   // 1 if some query advances this round
     uint32_t nslots;    // slots in use (upper bound of active slot ids)
     uint32_t err;       // device-side error bits
-    uint32_t pad[3];
+    uint32_t decided;   // low 32 bits of the dispatch-packet address of the last round launch that decided
+    uint32_t pad[2];
 };
 
 // Rotating counters: index (r % 3) holds the S and B item counts of the list

@@ -877,12 +877,13 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
     };
     double best = 1e300, t;
     uint32_t best_d = g->default_delta, best_l = 8, best_split = 0;
-    // a later candidate replaces the current choice only when it is clearly faster (3%), so repeated tunings of
-    // one graph settle on the same settings despite timing noise
+    // after the bucket width, a candidate replaces the default it competes with (depth 8, no split, the
+    // graph's pred placement, every resident workgroup) only when it is clearly faster (3%), so repeated
+    // tunings of one graph settle on the same settings despite timing noise
     auto better = [&](double tt) { return tt < best * 0.97; };
     for (uint32_t d : deltas) {
         if ((rc = measure(d, 8, 0, &t, lazy_default))) return rc;
-        if (better(t)) { best = t; best_d = d; }
+        if (t < best) { best = t; best_d = d; }
     }
     for (uint32_t l : {2u, 4u, 16u, 32u}) {
         if ((rc = measure(best_d, l, 0, &t, lazy_default))) return rc;

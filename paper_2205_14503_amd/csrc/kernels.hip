@@ -38,6 +38,7 @@ DEVI uint64_t ld_agent(const uint64_t *p) {
 DEVI uint32_t ld_agent(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+DEVI void st_agent(uint32_t *p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 // Orders LDS traffic between the lanes of one wave.
 DEVI void wave_sync() {
@@ -876,6 +877,17 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
         b3[i] = ld_agent(&P.cnt->b[i]);
     }
     if (done) return;
+    // A workgroup dispatched after this launch's decision (late, behind other kernels' workgroups) would read
+    // the next round's state above and could take part in it and count toward the wrong launch.  The decider
+    // publishes the launch's identity (the address of its dispatch packet in the queue, distinct for
+    // consecutive launches) before it changes that state; if it is visible after the acquire fence, the state
+    // read above may be the next round's and this workgroup leaves.  A workgroup that must take part is
+    // counted before any decision, so it never sees its own launch's identity here.  (A stale identity equal
+    // to this launch's, after the queue's ring has wrapped, makes every workgroup leave: a launch that changes
+    // nothing, the next one does the round.)
+    const uint32_t did = (uint32_t)(uintptr_t)__builtin_amdgcn_dispatch_ptr();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (ld_agent(&P.pass->decided) == did) return;
     const uint32_t cur = r % 3u;  // this round's list (the advance below fills the next one)
     // uniform values: scalar registers
     const uint32_t cs = (uint32_t)__builtin_amdgcn_readfirstlane(
@@ -912,7 +924,12 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    if (threadIdx.x == 0) { s_adv = 0; s_act = 0; }
+    if (threadIdx.x == 0) {
+        s_adv = 0;
+        s_act = 0;
+        __hip_atomic_store(&P.pass->decided, did, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // before any state a late workgroup reads
+    }
     __syncthreads();
     bool aa = false, act = false;
     const uint32_t nb = (r + 1) % 3u;
@@ -927,12 +944,12 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
     if (act) atomicOr(&s_act, 1);
     __syncthreads();
     if (threadIdx.x == 0) {
-        P.cnt->s[(r + 2) % 3u] = 0;
-        P.cnt->b[(r + 2) % 3u] = 0;
+        st_agent(&P.cnt->s[(r + 2) % 3u], 0u);
+        st_agent(&P.cnt->b[(r + 2) % 3u], 0u);
         P.cnt->blocks_done = 0;
-        P.pass->any_adv = s_adv;
-        if (!s_act) P.pass->all_done = 1;
-        P.pass->round = r + 1;
+        st_agent(&P.pass->any_adv, (uint32_t)s_adv);
+        if (!s_act) st_agent(&P.pass->all_done, 1u);
+        st_agent(&P.pass->round, r + 1);
         __threadfence();
     }
 }
@@ -1066,6 +1083,7 @@ __global__ void k_pass_reset(VorParams P) {
         P.pass->all_done = 1;  // no active query yet
         P.pass->any_adv = 0;
         P.pass->err = 0;
+        P.pass->decided = 0xFFFFFFFFu;
         for (int i = 0; i < 3; i++) { P.cnt->s[i] = 0; P.cnt->b[i] = 0; }
         P.cnt->bar_count = 0;
         P.cnt->bar_gen = 0;
@@ -1204,7 +1222,7 @@ DEVI int boundary_candidate(const DevGraph &g, uint64_t *pt, const uint32_t *tr,
 // row gathers its neighbour's key and pred is the qualifying neighbour of
 // smallest caller id; without, only entries a -> b with a < b do, unreached
 // rows included, which still sees every edge once for the overflow test.
-constexpr int SCAN_UNROLL = 2;
+constexpr int SCAN_UNROLL = 4;
 
 // Adds the wave's per-lane event counts to the scan counters (counting mode).
 DEVI void scan_count(unsigned long long *ev, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {

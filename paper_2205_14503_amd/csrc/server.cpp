@@ -200,6 +200,12 @@ void steiner_server::run_sched() {
     (void)hipSetDevice(g->device);
     uint8_t *hc = hbuf.as<uint8_t>();
     const uint32_t rounds_per_chunk = 4;
+    // every launch with a query resident takes its round's decision and advances the round counter; a chunk
+    // that leaves it unchanged, or a query resident for more rounds than any pass may take, means the pass
+    // state is broken: every request then fails instead of the scheduler relaunching rounds for ever
+    const uint32_t round_cap = 1u << 26;
+    uint32_t round_seen = 0;
+    std::vector<uint32_t> admitted_at(S, 0);
     std::unique_lock<std::mutex> lk(mu);
     while (!stopping) {
         // admission, first come first served
@@ -221,6 +227,7 @@ void steiner_server::run_sched() {
             used += need;
             slot_state[slot] = SLOT_ACTIVE;
             slot_req[slot] = r;
+            admitted_at[slot] = round_seen;
             const int rc = admit(r, slot);
             if (rc) fatal = rc;
         }
@@ -267,8 +274,14 @@ void steiner_server::run_sched() {
                            "D2H done");
         if (!rc) rc = hip_check(hipStreamSynchronize(s_main), "chunk sync");
         lk.lock();
-        if (!rc && (((PassCtl *)(hc + L.pass))->err & ERR_LIST_OVERFLOW))
-            rc = fail(STEINER_EDEVICE, "frontier overflow");
+        const PassCtl *hpass = (const PassCtl *)(hc + L.pass);
+        if (!rc && (hpass->err & ERR_LIST_OVERFLOW)) rc = fail(STEINER_EDEVICE, "frontier overflow");
+        if (!rc && hpass->round == round_seen)
+            rc = fail(STEINER_EDEVICE, "relaxation stalled at round %u", hpass->round);
+        if (!rc) round_seen = hpass->round;
+        for (uint32_t s = 0; s < S && !rc; s++)
+            if (slot_state[s] == SLOT_ACTIVE && round_seen - admitted_at[s] > round_cap)
+                rc = fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)", round_seen - admitted_at[s]);
         if (rc) {
             fatal = rc;
             continue;

@@ -22,6 +22,7 @@ static std::mutex g_alloc_mu;
 static std::unordered_map<void *, size_t> g_dev_sizes;  // live device allocations (not pinned host ones)
 static long g_live_dev_bytes = 0;
 static std::atomic<bool> g_stall{false};
+static std::atomic<bool> g_freeze{false};
 
 hipError_t hipSetDevice(int) { return hipSuccess; }
 hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
@@ -99,8 +100,10 @@ long hipsim_live_device_bytes() {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
     return g_live_dev_bytes;
 }
-// While set, relaxation rounds make no progress (queries stay unconverged).
+// While set, relaxation rounds advance the round counter but no query converges.
 void hipsim_stall(bool on) { g_stall.store(on); }
+// While set, relaxation launches change nothing at all, not even the round counter (a broken pass).
+void hipsim_freeze(bool on) { g_freeze.store(on); }
 
 namespace stn {
 
@@ -164,7 +167,11 @@ hipError_t launch_slot_start(const VorParams &P, uint32_t slot, const uint32_t *
 
 hipError_t launch_round(const VorParams &P, uint32_t, uint32_t, hipStream_t) {
     std::lock_guard<std::mutex> lk(sim_mu);
-    if (P.pass->all_done || g_stall.load()) return hipSuccess;
+    if (P.pass->all_done || g_freeze.load()) return hipSuccess;
+    if (g_stall.load()) {
+        P.pass->round++;
+        return hipSuccess;
+    }
     bool any = false;
     for (uint32_t q = 0; q < P.nslots; q++) {
         if (!P.slot.active[q]) continue;

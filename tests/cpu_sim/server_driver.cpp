@@ -12,6 +12,7 @@
 long hipsim_live_allocs();
 long hipsim_live_device_bytes();
 void hipsim_stall(bool on);
+void hipsim_freeze(bool on);
 
 // The renumbering's maps against the caller's CSR: perm is a permutation by
 // non-increasing degree and inv its inverse; every internal entry is a caller
@@ -134,6 +135,17 @@ static int server_memory_and_waits(steiner_graph *g) {
     w3.join();
     hipsim_stall(false);
     CHECK(rc2 == STEINER_ECANCELED && rc3 == STEINER_ECANCELED);
+    // a pass whose round counter stops moving fails the resident and the waiting requests instead of
+    // relaunching rounds for ever
+    CHECK(steiner_server_create(g, budget, 1, nullptr, &srv) == STEINER_OK);
+    hipsim_freeze(true);
+    CHECK(steiner_server_submit(srv, s2, 3, &t2) == STEINER_OK);
+    CHECK(steiner_server_submit(srv, s3, 2, &t3) == STEINER_OK);
+    steiner_result *x = nullptr;
+    CHECK(steiner_server_wait(srv, t2, 20000000, &x) == STEINER_EDEVICE && x == nullptr);
+    CHECK(steiner_server_wait(srv, t3, 20000000, &x) == STEINER_EDEVICE && x == nullptr);
+    hipsim_freeze(false);
+    CHECK(steiner_server_destroy(srv) == STEINER_OK);
     CHECK(hipsim_live_device_bytes() == before);
     return 0;
 }

@@ -1,7 +1,8 @@
 """Compile-time properties of the relaxation and boundary-scan kernels (no
 GPU needed): the relaxation's in-flight loads and atomics must stay in
 registers (no scratch spills) at four or more waves per SIMD, and the scan
-(bound by its memory traffic) keeps eight waves per SIMD."""
+(bound by the latency of its dependent loads) keeps seven waves per SIMD
+with four independent steps in flight."""
 import os
 import re
 import subprocess
@@ -34,5 +35,5 @@ def test_round_kernel_occupancy(tmp_path):
     scans = [v for k, v in info.items() if k.startswith("_ZN3stn6k_scan") and k.endswith("ELb0EEEvNS_10ScanParamsE")]
     assert len(scans) == 2, list(info)
     for scan in scans:
-        assert int(scan["Occupancy [waves/SIMD]"]) >= 8, scan
+        assert int(scan["Occupancy [waves/SIMD]"]) >= 7, scan
         assert int(scan["ScratchSize [bytes/lane]"]) == 0, scan
