@@ -154,6 +154,64 @@ def trace_summary(args):
           f"{rf['avg_launch_us']} us per launch (event pairs around chunks of launches, gaps included).")
 
 
+def _union_ms(iv):
+    """Length of the union of [start, end) nanosecond intervals, in ms."""
+    tot, cur_s, cur_e = 0, None, None
+    for a, b in sorted(iv):
+        if cur_e is None or a > cur_e:
+            if cur_e is not None:
+                tot += cur_e - cur_s
+            cur_s, cur_e = a, b
+        else:
+            cur_e = max(cur_e, b)
+    if cur_e is not None:
+        tot += cur_e - cur_s
+    return tot / 1e6
+
+
+def busy_summary(args):
+    """GPU-busy time of a batching or serving run under rocprofv3
+    --kernel-trace, phase by phase.  Phases are found from marker kernels:
+    every solve and every batch starts with one pass reset, and a server
+    starts with a pass reset followed by its slot-id fill (k_iota).  Serving
+    runs: the sequential phase is the last `queries` solves before the first
+    server; then one phase per offered rate.  Batch runs: the last `steps`
+    batches, then the sequential solves of the same queries."""
+    import csv
+    trace_csv, json_file = args.busy_summary
+    line = json.loads([x for x in open(json_file) if x.startswith("{")][-1])
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    ts = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows]
+    names = [_trace_name(r["Kernel_Name"]) for r in rows]
+    resets = [i for i, nm in enumerate(names) if nm == "stn::k_pass_reset"]
+    phases = []  # (label, queries, first row, end row)
+    if "serving" in line:
+        nq = line["config"]["queries"]
+        iotas = [i for i, r in enumerate(rows) if "k_iota(" in r["Kernel_Name"]]
+        srv = [max(j for j in resets if j < i) for i in iotas]
+        seq = [j for j in resets if j < srv[0]][-nq:]
+        phases.append(("sequential solves", nq, seq[0], srv[0]))
+        for p, (label, _) in enumerate(line["serving"]["rho"].items()):
+            phases.append((f"server, rho = {label}", nq, srv[p], srv[p + 1] if p + 1 < len(srv) else len(rows)))
+    else:
+        q, steps = line["config"]["queries"], line["steps"]
+        phases.append((f"batched pass ({steps} batches)", q * steps, resets[-q - steps], resets[-q]))
+        phases.append(("sequential solves", q, resets[-q], len(rows)))
+    print(f"Workload {line['config']['workload']}: {line['value']} {line['unit']} "
+          f"({'served' if 'serving' in line else 'batched'}), "
+          f"sequential {line['sequential_queries_per_s']} queries/s.\n")
+    print("| phase | queries | span ms | kernel ms | GPU busy ms | busy | kernel ms per query | "
+          "span ms per query | k_round launches | k_round avg us |\n|---|---|---|---|---|---|---|---|---|---|")
+    for label, nq, a, b in phases:
+        iv = ts[a:b]
+        span = (max(e for _, e in iv) - iv[0][0]) / 1e6
+        kern = sum(e - s for s, e in iv) / 1e6
+        busy = _union_ms(iv)
+        kr = [e - s for (s, e), nm in zip(iv, names[a:b]) if nm == "stn::k_round"]
+        print(f"| {label} | {nq} | {span:.1f} | {kern:.1f} | {busy:.1f} | {100 * busy / span:.1f}% | "
+              f"{kern / nq:.2f} | {span / nq:.2f} | {len(kr)} | {sum(kr) / max(len(kr), 1) / 1e3:.1f} |")
+
+
 def bench_sweep(args, st, W, np, torch, stream):
     """The paper's sensitivity studies on one GPU (RMAT scale `--sweep-scale`,
     edge factor 16): bucket width from Dijkstra-like to unbounded (its
@@ -355,6 +413,8 @@ def main():
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the workload's entry of profiles/traffic.json from rocprofv3 counter runs "
                          "(with the --delta and --local those runs used)")
+    ap.add_argument("--busy-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
+                    help="GPU-busy time per phase of a batching or serving run under rocprofv3")
     ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
                     help="per-kernel durations over the timed region of a bench.py run under rocprofv3")
     args = ap.parse_args()
@@ -363,6 +423,9 @@ def main():
         return
     if args.trace_summary:
         trace_summary(args)
+        return
+    if args.busy_summary:
+        busy_summary(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path.",

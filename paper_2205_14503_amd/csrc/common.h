@@ -47,8 +47,11 @@ struct PassCtl {
     uint32_t any_adv;   // 1 if some query advances this round
     uint32_t nslots;    // slots in use (upper bound of active slot ids)
     uint32_t err;       // device-side error bits
-    uint32_t decided;   // low 32 bits of the dispatch-packet address of the last round launch that decided
-    uint32_t pad[2];
+    uint32_t pad;
+    // The round kernel's view of round, any_adv and all_done, with the identity of the launch that last took a
+    // round decision, in one atomic word (bits 0-31 that launch's dispatch-packet address, 32-61 the round,
+    // 62 any_adv, 63 all_done); written with the fields above wherever they change.
+    uint64_t word;
 };
 
 // Rotating counters: index (r % 3) holds the S and B item counts of the list

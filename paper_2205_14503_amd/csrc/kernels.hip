@@ -38,7 +38,14 @@ DEVI uint64_t ld_agent(const uint64_t *p) {
 DEVI uint32_t ld_agent(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-DEVI void st_agent(uint32_t *p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+DEVI void st_agent(uint64_t *p, uint64_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// The pass's control word (PassCtl::word).
+DEVI uint64_t pass_word(uint32_t round, uint32_t any_adv, uint32_t all_done, uint32_t launch) {
+    return (uint64_t)launch | ((uint64_t)(round & 0x3FFFFFFFu) << 32) | ((uint64_t)(any_adv != 0) << 62) |
+           ((uint64_t)(all_done != 0) << 63);
+}
+constexpr uint32_t NO_LAUNCH = 0xFFFFFFFFu;
 
 // Orders LDS traffic between the lanes of one wave.
 DEVI void wave_sync() {
@@ -867,27 +874,24 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     WaveScratch *s_wave = (WaveScratch *)dyn_smem;
     __shared__ int s_last, s_adv, s_act;
-    // the pass state, all loads in flight together (the list counts of every buffer, selected after)
-    const uint32_t done = ld_agent(&P.pass->all_done), r = ld_agent(&P.pass->round);
-    const uint32_t any_adv = ld_agent(&P.pass->any_adv);
+    // The pass state, all loads in flight together (the list counts of every buffer, selected after).  A
+    // workgroup dispatched after this launch's decision (late, behind other kernels' workgroups) reads the next
+    // round's control word; were it to take part in that round inside this launch it would count toward the
+    // wrong launch.  The word carries the identity of the launch that decided last (its dispatch-packet address,
+    // distinct for consecutive launches), so such a workgroup sees its own launch's identity and leaves.  A
+    // workgroup that takes part is counted before any decision and never sees it.  The counts of this round's
+    // list do not change during the launch.  (A stale identity equal to this launch's, after the queue's ring
+    // has wrapped, makes every workgroup leave: the launch changes nothing and the next one does the round.)
+    const uint64_t pw = ld_agent(&P.pass->word);
     uint32_t s3[3], b3[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         s3[i] = ld_agent(&P.cnt->s[i]);
         b3[i] = ld_agent(&P.cnt->b[i]);
     }
-    if (done) return;
-    // A workgroup dispatched after this launch's decision (late, behind other kernels' workgroups) would read
-    // the next round's state above and could take part in it and count toward the wrong launch.  The decider
-    // publishes the launch's identity (the address of its dispatch packet in the queue, distinct for
-    // consecutive launches) before it changes that state; if it is visible after the acquire fence, the state
-    // read above may be the next round's and this workgroup leaves.  A workgroup that must take part is
-    // counted before any decision, so it never sees its own launch's identity here.  (A stale identity equal
-    // to this launch's, after the queue's ring has wrapped, makes every workgroup leave: a launch that changes
-    // nothing, the next one does the round.)
     const uint32_t did = (uint32_t)(uintptr_t)__builtin_amdgcn_dispatch_ptr();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (ld_agent(&P.pass->decided) == did) return;
+    if ((pw >> 63) || (uint32_t)pw == did) return;
+    const uint32_t r = (uint32_t)(pw >> 32) & 0x3FFFFFFFu, any_adv = (uint32_t)(pw >> 62) & 1u;
     const uint32_t cur = r % 3u;  // this round's list (the advance below fills the next one)
     // uniform values: scalar registers
     const uint32_t cs = (uint32_t)__builtin_amdgcn_readfirstlane(
@@ -924,12 +928,7 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    if (threadIdx.x == 0) {
-        s_adv = 0;
-        s_act = 0;
-        __hip_atomic_store(&P.pass->decided, did, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // before any state a late workgroup reads
-    }
+    if (threadIdx.x == 0) { s_adv = 0; s_act = 0; }
     __syncthreads();
     bool aa = false, act = false;
     const uint32_t nb = (r + 1) % 3u;
@@ -944,12 +943,13 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
     if (act) atomicOr(&s_act, 1);
     __syncthreads();
     if (threadIdx.x == 0) {
-        st_agent(&P.cnt->s[(r + 2) % 3u], 0u);
-        st_agent(&P.cnt->b[(r + 2) % 3u], 0u);
+        P.cnt->s[(r + 2) % 3u] = 0;
+        P.cnt->b[(r + 2) % 3u] = 0;
         P.cnt->blocks_done = 0;
-        st_agent(&P.pass->any_adv, (uint32_t)s_adv);
-        if (!s_act) st_agent(&P.pass->all_done, 1u);
-        st_agent(&P.pass->round, r + 1);
+        P.pass->any_adv = s_adv;
+        if (!s_act) P.pass->all_done = 1;
+        P.pass->round = r + 1;
+        st_agent(&P.pass->word, pass_word(r + 1, s_adv, !s_act, did));
         __threadfence();
     }
 }
@@ -1063,6 +1063,8 @@ __global__ void __launch_bounds__(256) k_persistent(VorParams P, uint32_t max_ro
         if (threadIdx.x == 0) {
             P.pass->round = r;
             if (finished) P.pass->all_done = 1;
+            P.pass->any_adv = 0;
+            P.pass->word = pass_word(r, 0, P.pass->all_done, NO_LAUNCH);
             (void)ok;
         }
     }
@@ -1083,7 +1085,7 @@ __global__ void k_pass_reset(VorParams P) {
         P.pass->all_done = 1;  // no active query yet
         P.pass->any_adv = 0;
         P.pass->err = 0;
-        P.pass->decided = 0xFFFFFFFFu;
+        P.pass->word = pass_word(0, 0, 1, NO_LAUNCH);
         for (int i = 0; i < 3; i++) { P.cnt->s[i] = 0; P.cnt->b[i] = 0; }
         P.cnt->bar_count = 0;
         P.cnt->bar_gen = 0;
@@ -1160,6 +1162,7 @@ __global__ void k_slot_seed(VorParams P, uint32_t slot, const uint32_t *seeds, u
             P.settle_mark[(size_t)b * P.nslots + slot] = 0;
         }
         P.pass->all_done = 0;
+        P.pass->word &= ~(1ull << 63);
     }
 }
 

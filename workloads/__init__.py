@@ -291,6 +291,9 @@ WORKLOADS = {
     # batching where one query leaves the GPU mostly idle (high diameter: latency bound)
     "grid2048_batch32": dict(kind="grid", rows=2048, cols=2048, wlo=1, whi=1000, queries=32, k_lo=10, k_hi=1000,
                              seeds_from="all"),
+    # serving where one query leaves the GPU mostly idle
+    "grid2048_serve": dict(kind="grid", rows=2048, cols=2048, wlo=1, whi=1000, k_lo=10, k_hi=1000,
+                           seeds_from="all"),
 }
 
 
