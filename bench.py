@@ -80,9 +80,9 @@ def _pmc_per_kernel(path: str):
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
-def _config_key(delta, local, split=None, grid=0) -> str:
+def _config_key(delta, local, split=None, grid=0, defer=False) -> str:
     key = f"delta={int(delta)},local_iters={int(local)},split={split or 0}"
-    return key + (f",grid={int(grid)}" if grid else "")
+    return key + (f",grid={int(grid)}" if grid else "") + (",defer=1" if defer else "")
 
 
 def pmc_summary(args):
@@ -108,7 +108,8 @@ def pmc_summary(args):
             lines.append(f"| {name} | {cnt} | {fv:.1f} | {wv:.1f} | {mb:.3f} |")
     entry["bytes_per_launch"] = entry["per_kernel"]["k_round"]["bytes"]
     data = json.load(open(TRAFFIC_FILE)) if os.path.exists(TRAFFIC_FILE) else {}
-    data.setdefault(args.workload, {})[_config_key(args.delta, args.local, args.split, args.grid)] = entry
+    data.setdefault(args.workload, {})[_config_key(args.delta, args.local, args.split, args.grid,
+                                                    args.defer == "on")] = entry
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
     print(f"Copy calibration: a 1 GiB device copy reads {copy_kib / f_scale:.1f} KiB of FETCH_SIZE "
@@ -404,6 +405,8 @@ def main():
     ap.add_argument("--budget-gb", type=int, default=96, help="serving: device memory budget")
     ap.add_argument("--local", type=int, default=0, help="local-queue depth (with --delta: skips the tuner)")
     ap.add_argument("--grid", type=int, default=0, help="relaxation workgroups (with --delta: skips the tuner)")
+    ap.add_argument("--defer", default=None, choices=["on", "off"],
+                    help="large rows expanded at the bucket's advance (with --delta: skips the tuner)")
     ap.add_argument("--split", default=None, choices=["weight"],
                     help="light/heavy edge split (with --delta: skips the tuner)")
     ap.add_argument("--seeds", default="uniform", help="seed strategy: uniform, bfs_level, eccentric, proximate")
@@ -474,6 +477,8 @@ def main():
         opts["grid"] = args.grid
     if args.split:
         opts["flags"] |= st.FLAG_SPLIT
+    if args.defer:
+        opts["flags"] |= st.FLAG_DEFER if args.defer == "on" else st.FLAG_NO_DEFER
     dg = st.Graph(g, 0, stream)
     tuned = None
     if not args.no_tune and not args.delta:
@@ -482,7 +487,7 @@ def main():
         split = "weight" if tuned["flags"] & st.FLAG_SPLIT else None
         tuned = {"delta": tuned["delta"], "local_iters": tuned["local_iters"], "grid": tuned["grid"],
                  "split": split, "lazy_pred": bool(tuned["flags"] & st.FLAG_LAZY_PRED),
-                 "seconds": round(time.time() - t0, 2)}
+                 "defer": bool(tuned["flags"] & st.FLAG_DEFER), "seconds": round(time.time() - t0, 2)}
         print(f"[bench] tuned {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         tree = dg.solve(seeds, opts)
@@ -522,7 +527,9 @@ def main():
             local = opts.get("local_iters", tuned and tuned["local_iters"])
             split = args.split or (tuned and tuned["split"])
             grid = opts.get("grid", tuned["grid"] if tuned else 0)
-            ent = json.load(open(TRAFFIC_FILE)).get(args.workload, {}).get(_config_key(delta, local, split, grid))
+            defer = args.defer == "on" if args.defer else bool(tuned and tuned["defer"])
+            ent = json.load(open(TRAFFIC_FILE)).get(args.workload, {}).get(
+                _config_key(delta, local, split, grid, defer))
             if ent and ent.get("kernel_sha") == kernel_sha():
                 traffic = ent["bytes_per_launch"]
         except Exception:

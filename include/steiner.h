@@ -91,6 +91,11 @@ typedef struct steiner_options {
                                       walks find the preds of ordinary rows (dense graphs) */
 #define STEINER_FLAG_EAGER_PRED 16u /* the boundary scan also finds every pred (sparse, high-diameter
                                        graphs); without either flag the graph's default applies */
+#define STEINER_FLAG_DEFER 32u    /* a row of more than small_max entries whose distance improves inside the
+                                     open bucket is expanded once, when the bucket advances, instead of in the
+                                     next round (fewer re-expansions of hubs); ignored with the split */
+#define STEINER_FLAG_NO_DEFER 64u /* expand such rows in the next round; without either flag the graph's
+                                     default applies (deferral on degree-renumbered graphs) */
 
 /* Per-solve statistics (filled for steiner_solve / steiner_solve_batch results). */
 typedef struct steiner_stats {

@@ -32,6 +32,8 @@ FLAG_COUNTERS = 2
 FLAG_SPLIT = 4
 FLAG_LAZY_PRED = 8
 FLAG_EAGER_PRED = 16
+FLAG_DEFER = 32
+FLAG_NO_DEFER = 64
 MAX_SEEDS = 92682
 UPLOAD_SYMMETRY = 1
 UPLOAD_REORDER = 2

@@ -140,6 +140,7 @@ struct VorParams {
     uint32_t counting;    // 1: accumulate Counters::ev
     uint32_t split;       // 1: light/heavy edge split (finite delta)
     uint32_t lq_mode;     // bit 0: drain the local queue smallest distance first; bit 1: skip superseded entries
+    uint32_t defer_min;   // improved rows above this many entries wait for the bucket's advance (0: never)
     // Chunk memory (null when off): the rows above small_max are the vertices below nxrow (a degree-renumbered
     // graph) and chunk c of row v is chunk number xchunk[v] + c of xchunks per query; xkey[slot * xchunks + i]
     // is the key chunk i was last expanded with (all ones: never).  A chunk whose row still holds that key

@@ -141,11 +141,15 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
     r.counting = false;
     r.split = g->tuned_split != 0;
     r.lq_mode = 3;  // local queue drained smallest distance first, superseded entries skipped
+    // deferring the expansion of improved large rows to the bucket's advance pays on skewed graphs (the ones
+    // renumbered by degree), whose hubs are otherwise expanded about twice per solve
+    bool defer = g->tuned_defer ? g->tuned_defer == 2 : g->reordered;
     // lazy preds pay one row scan per tree vertex to save half the scan's gathers: a win on
     // dense graphs, a loss on sparse high-diameter ones (long walks, cheap scan)
     r.lazy_pred = g->tuned_pred ? g->tuned_pred == 2 : (g->n && (double)g->nnz / g->n >= 8.0);
     if (const char *s = getenv("STEINER_LAZY_PRED")) r.lazy_pred = atoi(s) != 0;
     if (const char *s = getenv("STEINER_LQ_MODE")) r.lq_mode = (uint32_t)atoi(s);
+
     if (const char *s = getenv("STEINER_DRIVER")) r.driver = (uint32_t)atoi(s);
     if (const char *s = getenv("STEINER_LOCAL")) r.local_iters = (uint32_t)strtoul(s, nullptr, 10);
     if (const char *s = getenv("STEINER_DELTA")) r.delta = (uint32_t)strtoul(s, nullptr, 10);
@@ -162,7 +166,11 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
         if (o->flags & STEINER_FLAG_SPLIT) r.split = true;
         if (o->flags & STEINER_FLAG_LAZY_PRED) r.lazy_pred = true;
         if (o->flags & STEINER_FLAG_EAGER_PRED) r.lazy_pred = false;
+        if (o->flags & STEINER_FLAG_DEFER) defer = true;
+        if (o->flags & STEINER_FLAG_NO_DEFER) defer = false;
     }
+    r.defer_min = defer ? std::max<uint32_t>(r.small_max, 1) : 0;
+    if (const char *s = getenv("STEINER_DEFER")) r.defer_min = (uint32_t)strtoul(s, nullptr, 10);
     if (r.delta == 0) r.delta = 1;
     if (r.block < 64 || r.block > 1024 || r.block % 64) r.block = 256;
     if (r.block > 256) r.block = 256;  // per-wave LDS scratch of the relaxation kernels (~10 KB per wave)
@@ -846,19 +854,22 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
     if ((rc = canon_seeds(g, seeds, k, S))) return rc;
     if (S.size() < 2) return fail(STEINER_EINVAL, "tuning needs at least 2 distinct seeds");
     const double w = std::max(1.0, g->avg_w);
-    std::vector<uint32_t> deltas = {g->classic_delta, (uint32_t)std::max(1.0, w / 4), (uint32_t)std::max(1.0, w),
+    std::vector<uint32_t> deltas = {g->classic_delta, (uint32_t)std::max(1.0, w / 4), (uint32_t)std::max(1.0, w / 2),
+                                    (uint32_t)std::max(1.0, w),
                                     (uint32_t)std::max(1.0, 4 * w), (uint32_t)std::max(1.0, 16 * w), 0xFFFFFFFFu};
     std::sort(deltas.begin(), deltas.end());
     deltas.erase(std::unique(deltas.begin(), deltas.end()), deltas.end());
     // coarse to fine: the bucket width at the default queue depth, then the depth, then the split
     const bool lazy_default = resolve_options(g, nullptr).lazy_pred;
     g->tuned_grid = 0;
-    auto measure = [&](uint32_t d, uint32_t l, uint32_t split, double *t_out, bool lazy, uint32_t grid = 0) -> int {
+    auto measure = [&](uint32_t d, uint32_t l, uint32_t split, double *t_out, bool lazy, uint32_t grid = 0,
+                       int defer = -1) -> int {
         Options o = resolve_options(g, nullptr);
         o.delta = d;
         o.local_iters = l;
         o.split = split != 0 && d != 0xFFFFFFFFu;
         o.lazy_pred = lazy;
+        if (defer >= 0) o.defer_min = defer ? std::max<uint32_t>(o.small_max, 1) : 0;
         if (grid) o.grid = o.grid_tuned = grid;
         double t_min = 1e300;
         for (int rep = 0; rep < 2; rep++) {
@@ -877,24 +888,28 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
     };
     double best = 1e300, t;
     uint32_t best_d = g->default_delta, best_l = 8, best_split = 0;
+    // deferral is tried beside each bucket width wherever some row exceeds the small-row bound
+    const bool can_defer = g->max_deg > resolve_options(g, nullptr).small_max;
+    int best_defer = 0;
     // after the bucket width, a candidate replaces the default it competes with (depth 8, no split, the
     // graph's pred placement, every resident workgroup) only when it is clearly faster (3%), so repeated
     // tunings of one graph settle on the same settings despite timing noise
     auto better = [&](double tt) { return tt < best * 0.97; };
-    for (uint32_t d : deltas) {
-        if ((rc = measure(d, 8, 0, &t, lazy_default))) return rc;
-        if (t < best) { best = t; best_d = d; }
-    }
+    for (uint32_t d : deltas)
+        for (int df = 0; df <= (can_defer ? 1 : 0); df++) {
+            if ((rc = measure(d, 8, 0, &t, lazy_default, 0, df))) return rc;
+            if (t < best) { best = t; best_d = d; best_defer = df; }
+        }
     for (uint32_t l : {2u, 4u, 16u, 32u}) {
-        if ((rc = measure(best_d, l, 0, &t, lazy_default))) return rc;
+        if ((rc = measure(best_d, l, 0, &t, lazy_default, 0, best_defer))) return rc;
         if (better(t)) { best = t; best_l = l; }
     }
-    if (best_d != 0xFFFFFFFFu) {
-        if ((rc = measure(best_d, best_l, 1, &t, lazy_default))) return rc;
-        if (better(t)) { best = t; best_split = 1; }
+    if (best_d != 0xFFFFFFFFu) {  // the split expands every settled row's heavy edges at the advance: no deferral
+        if ((rc = measure(best_d, best_l, 1, &t, lazy_default, 0, 0))) return rc;
+        if (better(t)) { best = t; best_split = 1; best_defer = 0; }
     }
     bool best_lazy = lazy_default;
-    if ((rc = measure(best_d, best_l, best_split, &t, !lazy_default))) return rc;
+    if ((rc = measure(best_d, best_l, best_split, &t, !lazy_default, 0, best_defer))) return rc;
     if (better(t)) { best = t; best_lazy = !lazy_default; }
     // then fewer relaxation workgroups (a quarter to three quarters of the resident count), at the chosen depth
     // and at 8
@@ -906,7 +921,7 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
         for (uint32_t l : ls)
             for (uint32_t gsz : {(uint32_t)resident / 4, (uint32_t)resident * 3 / 8, (uint32_t)resident / 2,
                                  (uint32_t)resident * 3 / 4}) {
-                if ((rc = measure(best_d, l, best_split, &t, best_lazy, gsz))) return rc;
+                if ((rc = measure(best_d, l, best_split, &t, best_lazy, gsz, best_defer))) return rc;
                 if (better(t)) { best = t; best_l = l; best_grid = gsz; }
             }
     }
@@ -915,12 +930,14 @@ extern "C" int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint3
     g->tuned_local = best_l;
     g->tuned_split = best_split;
     g->tuned_pred = best_lazy ? 2 : 1;
+    g->tuned_defer = best_defer ? 2 : 1;
     if (out) {
         memset(out, 0, sizeof(*out));
         out->delta = best_d;
         out->local_iters = best_l;
         out->grid = best_grid;
-        out->flags = (best_split ? STEINER_FLAG_SPLIT : 0u) | (best_lazy ? STEINER_FLAG_LAZY_PRED : STEINER_FLAG_EAGER_PRED);
+        out->flags = (best_split ? STEINER_FLAG_SPLIT : 0u) | (best_lazy ? STEINER_FLAG_LAZY_PRED : STEINER_FLAG_EAGER_PRED) |
+                     (best_defer ? STEINER_FLAG_DEFER : STEINER_FLAG_NO_DEFER);
     }
     return STEINER_OK;
 }

@@ -42,6 +42,7 @@ struct HostPinned {
 
 struct Options {
     uint32_t delta, driver, block, grid, small_max, chunk, local_iters, lq_mode;
+    uint32_t defer_min;   // improved rows above this many entries are expanded at the bucket's advance (0: never)
     uint32_t grid_tuned;  // relaxation workgroups of a host-stepped pass (the tuned count unless given)
     bool timing, counting, split;
     bool lazy_pred;  // pred of ordinary rows found by the tree walks instead of the scan
@@ -196,6 +197,7 @@ struct steiner_graph {
     uint32_t tuned_local = 0;
     uint32_t tuned_split = 0;
     uint32_t tuned_pred = 0;     // 0: untuned, 1: eager, 2: lazy
+    uint32_t tuned_defer = 0;    // 0: untuned, 1: large rows expanded in the next round, 2: at the bucket's advance
     uint32_t tuned_grid = 0;     // relaxation workgroups of a host-stepped pass (0: as many as are resident)
     uint32_t last_rounds = 0;    // relaxation rounds of the previous pass (sizes the first launch chunk)
     double avg_w = 1.0;

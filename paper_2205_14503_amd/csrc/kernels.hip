@@ -255,6 +255,14 @@ DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr
 #pragma unroll
     for (int i = 0; i < UNROLL; i++) {
         deg[i] -= beg[i];
+        // deferred large row: expanded once, at the bucket's advance, instead of at every improvement
+        const bool defer = P.defer_min && near[i] && deg[i] > P.defer_min;
+        if (defer) {
+            P.settled[(size_t)slot[i] * n + u[i]] = 1;
+            uint32_t *sm = P.settle_mark + (size_t)R.b * P.nslots + slot[i];
+            if (*sm == 0) *sm = 1;
+            near[i] = false;
+        }
         bool local = false;
         if (L) {
             const bool want = near[i] && deg[i] <= P.small_max;
@@ -835,6 +843,11 @@ DEVI void advance_body(const VorParams &P, const uint64_t *thr, const uint64_t *
                     P.settled[o] = 0;
                     deg = P.g.rp[v + 1] - P.g.rp[v];
                     hpush = true;
+                } else if (!P.split && P.settled[o]) {  // a large row deferred to the bucket's end
+                    P.settled[o] = 0;
+                    P.aux[o] = stamp;
+                    deg = P.g.rp[v + 1] - P.g.rp[v];
+                    push = true;
                 } else if (P.dirty[o]) {
                     const uint32_t d = (uint32_t)(ld_agent(P.key + o) >> 32);
                     if (d < lo) {

@@ -111,6 +111,7 @@ void bind_state(VorParams &P, const Options &o, uint64_t cap_s, uint64_t cap_b) 
     P.counting = o.counting ? 1u : 0u;
     P.split = (o.delta != 0xFFFFFFFFu && o.split) ? 1u : 0u;
     P.lq_mode = o.lq_mode;
+    P.defer_min = (o.split || !o.defer_min) ? 0 : std::max(o.defer_min, o.small_max);
 }
 
 namespace {

@@ -32,6 +32,11 @@ OPTION_SETS = {
     "split_chunky": dict(delta=7, flags=st.FLAG_SPLIT, small_max=1, chunk=64, local_iters=0xFFFFFFFF),
     "graph": dict(driver=4),
     "graph_bucketed": dict(driver=4, delta=50, local_iters=2),
+    "defer": dict(delta=50, flags=st.FLAG_DEFER),
+    "defer_chunky": dict(delta=7, small_max=1, chunk=64, flags=st.FLAG_DEFER),
+    "defer_unbounded": dict(delta=0xFFFFFFFF, flags=st.FLAG_DEFER),
+    "defer_persistent": dict(driver=2, delta=50, small_max=2, flags=st.FLAG_DEFER),
+    "no_defer": dict(flags=st.FLAG_NO_DEFER),
 }
 
 

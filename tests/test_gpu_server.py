@@ -41,6 +41,9 @@ SERVER_OPTIONS = {
     "no_local_queue": dict(local_iters=0xFFFFFFFF),
     "split_chunky": dict(delta=7, flags=st.FLAG_SPLIT, small_max=1, chunk=64, local_iters=0xFFFFFFFF),
     "graph": dict(driver=4),
+    "defer": dict(delta=50, flags=st.FLAG_DEFER),
+    "defer_chunky": dict(delta=7, small_max=1, chunk=64, flags=st.FLAG_DEFER),
+    "no_defer": dict(flags=st.FLAG_NO_DEFER),
 }
 
 
