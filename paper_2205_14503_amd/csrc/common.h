@@ -41,6 +41,12 @@ struct SlotArrays {
 };
 
 // Pass-wide control block (one per multi-query pass).
+// Round numbers wrap at a multiple of 6, so that the list parity (r & 1) and the rotating counters (r % 3)
+// continue across the wrap in a pass that lives for ever (the server's), and the round fits the 30 bits it has
+// in PassCtl::word.
+constexpr uint32_t ROUND_WRAP = 3u << 28;
+__host__ __device__ inline uint32_t next_round(uint32_t r) { return r + 1 == ROUND_WRAP ? 0u : r + 1; }
+
 struct PassCtl {
     uint32_t round;     // current round r
     uint32_t all_done;  // 1 when no resident query has work left
@@ -53,6 +59,11 @@ struct PassCtl {
     // 62 any_adv, 63 all_done); written with the fields above wherever they change.
     uint64_t word;
 };
+constexpr uint32_t NO_LAUNCH = 0xFFFFFFFFu;
+__host__ __device__ inline uint64_t pass_word(uint32_t round, uint32_t any_adv, uint32_t all_done, uint32_t launch) {
+    return (uint64_t)launch | ((uint64_t)(round & 0x3FFFFFFFu) << 32) | ((uint64_t)(any_adv != 0) << 62) |
+           ((uint64_t)(all_done != 0) << 63);
+}
 
 // Rotating counters: index (r % 3) holds the S and B item counts of the list
 // that round r processes; (r + 1) % 3 is filled during round r; (r + 2) % 3 is

@@ -40,12 +40,6 @@ DEVI uint32_t ld_agent(const uint32_t *p) {
 }
 DEVI void st_agent(uint64_t *p, uint64_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
-// The pass's control word (PassCtl::word).
-DEVI uint64_t pass_word(uint32_t round, uint32_t any_adv, uint32_t all_done, uint32_t launch) {
-    return (uint64_t)launch | ((uint64_t)(round & 0x3FFFFFFFu) << 32) | ((uint64_t)(any_adv != 0) << 62) |
-           ((uint64_t)(all_done != 0) << 63);
-}
-constexpr uint32_t NO_LAUNCH = 0xFFFFFFFFu;
 
 // Orders LDS traffic between the lanes of one wave.
 DEVI void wave_sync() {
@@ -961,8 +955,9 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
         P.cnt->blocks_done = 0;
         P.pass->any_adv = s_adv;
         if (!s_act) P.pass->all_done = 1;
-        P.pass->round = r + 1;
-        st_agent(&P.pass->word, pass_word(r + 1, s_adv, !s_act, did));
+        const uint32_t nr = next_round(r);
+        P.pass->round = nr;
+        st_agent(&P.pass->word, pass_word(nr, s_adv, !s_act, did));
         __threadfence();
     }
 }
@@ -1057,7 +1052,7 @@ __global__ void __launch_bounds__(256) k_persistent(VorParams P, uint32_t max_ro
                          nwaves, &s_wave[w]);
             if (!(ok = grid_barrier(P.cnt, gridDim.x, P.pass, &s_abort))) break;
         }
-        r++;
+        r = next_round(r);
         if (!any_act) {
             finished = true;
             break;

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -92,6 +93,12 @@ __global__ void k_set_slot_tables(uint64_t *pt_ptr, uint64_t *pt_len, uint64_t *
     out_cnt[slot] = 0;
 }
 
+// Starts the pass at round r (a long-lived pass runs through the wrap of the round numbers).
+__global__ void k_set_round(PassCtl *pass, uint32_t r) {
+    pass->round = r;
+    pass->word = pass_word(r, 0, 1, NO_LAUNCH);
+}
+
 __global__ void k_iota(uint32_t *p, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = i;
 }
@@ -105,6 +112,7 @@ struct steiner_server {
     // (per-slot vertex state and frontier lists) + the pool (per-request regions) = budget.
     uint64_t budget = 0, fixed_bytes = 0, slot_bytes = 0, pool_bytes = 0, used = 0;
     uint32_t S = 0;  // slots
+    uint32_t round_base = 0;  // the pass's first round (0 unless STEINER_SERVER_ROUND_BASE says otherwise)
     hipStream_t s_main = nullptr, s_tail = nullptr;
     DevBuf key, aux, dirty, settled, items_s[2], items_b[2], ctl, heavy_pe, pool, xkey;
     TailScratch tail;
@@ -204,7 +212,8 @@ void steiner_server::run_sched() {
     // that leaves it unchanged, or a query resident for more rounds than any pass may take, means the pass
     // state is broken: every request then fails instead of the scheduler relaunching rounds for ever
     const uint32_t round_cap = 1u << 26;
-    uint32_t round_seen = 0;
+    uint32_t round_seen = round_base;
+    auto rounds_since = [](uint32_t now, uint32_t then) { return (now + ROUND_WRAP - then) % ROUND_WRAP; };
     std::vector<uint32_t> admitted_at(S, 0);
     std::unique_lock<std::mutex> lk(mu);
     while (!stopping) {
@@ -280,8 +289,9 @@ void steiner_server::run_sched() {
             rc = fail(STEINER_EDEVICE, "relaxation stalled at round %u", hpass->round);
         if (!rc) round_seen = hpass->round;
         for (uint32_t s = 0; s < S && !rc; s++)
-            if (slot_state[s] == SLOT_ACTIVE && round_seen - admitted_at[s] > round_cap)
-                rc = fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)", round_seen - admitted_at[s]);
+            if (slot_state[s] == SLOT_ACTIVE && rounds_since(round_seen, admitted_at[s]) > round_cap)
+                rc = fail(STEINER_EDEVICE, "relaxation did not converge (%u rounds)",
+                          rounds_since(round_seen, admitted_at[s]));
         if (rc) {
             fatal = rc;
             continue;
@@ -471,6 +481,11 @@ extern "C" int steiner_server_create(steiner_graph *g, uint64_t mem_budget_bytes
         if ((rc = bind_chunk_memory(P, g, s->o, S, s->xkey))) return rc;  // the exact buffer made above
     }
     if ((rc = hip_check(launch_pass_reset(P, s->s_main), "pass reset"))) return rc;
+    if (const char *e = getenv("STEINER_SERVER_ROUND_BASE")) {  // testing the wrap of the round numbers
+        s->round_base = (uint32_t)(strtoull(e, nullptr, 10) % ROUND_WRAP);
+        hipLaunchKernelGGL(k_set_round, dim3(1), dim3(1), 0, s->s_main, P.pass, s->round_base);
+        if ((rc = hip_check(hipGetLastError(), "round base"))) return rc;
+    }
     if ((rc = hip_check(launch_fill_u32(s->tail.mark.as<uint32_t>(), mark_bytes / 4, 0u, s->s_main), "mark clear")))
         return rc;
     s->tail.mark_n = n;

@@ -179,6 +179,26 @@ def test_server_fixed_stride_rows(graph):
             assert gg.solve(s).edges == tree.edges
 
 
+def test_server_round_wrap(graph, monkeypatch):
+    """A server's pass lives for ever, so its round numbers wrap (at 3 * 2^28, a multiple of the list parity and
+    of the three rotating counters): a pass started just below the wrap serves every query through it with the
+    results of the same queries solved alone."""
+    g, cand, dg = graph
+    monkeypatch.setenv("STEINER_SERVER_ROUND_BASE", str((3 << 28) - 7))
+    ks = [2, 40, 600, 9, 150, 1200, 3, 64]
+    sets = [W.sample(cand, k, master=15, stream=700 + q) for q, k in enumerate(ks)]
+    for opt in (None, dict(delta=50)):
+        say(f"server round wrap ({opt}): 8 queries, 3 slots")
+        srv = st.steiner_server_create(dg.handle, 2 << 30, 3, opt)
+        try:
+            tickets = [st.steiner_server_submit(srv, s) for s in sets]
+            trees = [st.steiner_server_wait(srv, t) for t in tickets]
+        finally:
+            st.steiner_server_destroy(srv)
+        for q, (s, tree) in enumerate(zip(sets, trees)):
+            assert tree.edges == dg.solve(s, opt).edges, f"query {q} (k={ks[q]})"
+
+
 def test_server_timeout_and_cancel(graph):
     """A wait that runs out of time returns ETIMEDOUT and leaves the request
     pending; waiters blocked when the server is destroyed get ECANCELED."""
