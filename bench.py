@@ -60,6 +60,25 @@ def copy_calibration(torch, mib: int = 1024, reps: int = 3):
           flush=True)
 
 
+def gather_probe(torch, n: int, m: int = 1 << 26, reps: int = 5) -> float:
+    """Random 8-byte gathers per second of a plain torch index_select from an n-entry int64 array (the size of
+    one query's key array) at m uniformly random positions."""
+    x = torch.arange(n, dtype=torch.int64, device="cuda")
+    idx = torch.randint(0, n, (m,), dtype=torch.int64, device="cuda")
+    out = torch.empty(m, dtype=torch.int64, device="cuda")
+    torch.index_select(x, 0, idx, out=out)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.index_select(x, 0, idx, out=out)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del x, idx, out
+    return m / best
+
+
 def kernel_sha() -> str:
     """Hash of the sources that decide what the relaxation kernel does."""
     h = hashlib.sha256()
@@ -489,6 +508,11 @@ def main():
                  "split": split, "lazy_pred": bool(tuned["flags"] & st.FLAG_LAZY_PRED),
                  "defer": bool(tuned["flags"] & st.FLAG_DEFER), "seconds": round(time.time() - t0, 2)}
         print(f"[bench] tuned {tuned}", file=sys.stderr, flush=True)
+    # Before the warm-up, outside the timed region: the relaxation's random reads (one key read per attempt,
+    # counted in a solve of its own) and a plain random gather over an array of the same size, the rate that
+    # bounds them.
+    attempts = dg.solve(seeds, dict(opts, flags=opts["flags"] | st.FLAG_COUNTERS)).stats["relax_attempts"]
+    probe_gps = gather_probe(torch, g.n)
     for _ in range(args.warmup):
         tree = dg.solve(seeds, opts)
     torch.cuda.synchronize()
@@ -538,6 +562,11 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "algorithmic_bytes_per_step": kbytes, "launches_per_step": kl,
                 "avg_launch_us": round(kms / kl * 1e3, 3)}
+    roofline["random_access"] = {
+        "relax_attempts_per_step": attempts,
+        "relax_attempts_per_s": round(attempts / (mean_relax * 1e-3)),
+        "probe_gathers_per_s": round(probe_gps),
+        "probe": f"torch index_select of 2^26 random positions of a {g.n}-entry int64 array"}
 
     cpu, oracle_check = None, None
     if not args.no_cpu_baseline:
