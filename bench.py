@@ -243,11 +243,12 @@ def bench_sweep(args, st, W, np, torch, stream):
     rows = []
 
     def measure(dg, seeds, opts, **tags):
-        dg.solve(seeds, dict(opts, flags=flags))
+        o = dict(opts, flags=flags | opts.get("flags", 0))
+        dg.solve(seeds, o)
         ts, last = [], None
         for _ in range(3):
             t0 = time.perf_counter()
-            last = dg.solve(seeds, dict(opts, flags=flags))
+            last = dg.solve(seeds, o)
             ts.append((time.perf_counter() - t0) * 1e3)
         x = last.stats
         row = dict(tags, ms=round(float(np.median(ts)), 3), voronoi_ms=round(x["ms_voronoi"], 3),
@@ -264,8 +265,10 @@ def bench_sweep(args, st, W, np, torch, stream):
     dg = st.Graph(g, 0, stream)
     seeds = W.sample(cand, 1000, 1, W.STREAM_SEEDS)
     for delta in (1, 16, 128, 500, 2000, 8000, 0xFFFFFFFF):
-        measure(dg, seeds, {"delta": delta}, study="bucket width", weights="[1,1000]", k=1000,
-                delta="unbounded" if delta == 0xFFFFFFFF else delta)
+        for defer in ("off", "on"):  # large rows expanded in the next round / at the bucket's advance
+            measure(dg, seeds, {"delta": delta, "flags": st.FLAG_DEFER if defer == "on" else st.FLAG_NO_DEFER},
+                    study="bucket width", weights="[1,1000]", k=1000,
+                    delta="unbounded" if delta == 0xFFFFFFFF else delta, defer=defer)
     for k in (10, 100, 1000, 10000):
         s = W.sample(cand, k, 1, W.STREAM_SEEDS)
         tuned = dg.tune(s)
@@ -283,7 +286,7 @@ def bench_sweep(args, st, W, np, torch, stream):
             measure(dg, s, {"delta": delta}, study="weight range", weights=f"[1,{whi}]", k=1000,
                     delta="unbounded" if delta == 0xFFFFFFFF else delta)
         dg.close()
-    cols = ["study", "weights", "k", "delta", "strategy", "ms", "voronoi_ms", "scan_ms", "rounds", "messages",
+    cols = ["study", "weights", "k", "delta", "defer", "strategy", "ms", "voronoi_ms", "scan_ms", "rounds", "messages",
             "atomics", "improved", "tree_edges", "D"]
     print(f"RMAT scale {scale}, edge factor 16 ({g.n} vertices), one MI355X; messages = relaxation attempts.\n")
     print("| " + " | ".join(cols) + " |\n|" + "---|" * len(cols))
