@@ -4,6 +4,7 @@ All arithmetic is integer, so every comparison is exact: Voronoi keys
 (dist << 32 | seed index), canonical predecessors, the entries of G'1, the
 tree's edge list, D, and the status code.
 """
+import os
 import sys
 
 import numpy as np
@@ -86,6 +87,22 @@ def check_case(g, seeds, stream, options, what="", flags=0):
                 gi, gj, gk = dg.boundary(seeds, options)
                 assert np.array_equal(gi, pi) and np.array_equal(gj, pj), f"{what}: G'1 pairs differ"
                 assert np.array_equal(gk, (pb << np.uint64(32)) | pe.astype(np.uint64)), f"{what}: G'1 values differ"
+
+
+def test_golden_cases(stream):
+    """The hand-worked cases of tests/golden: every option set, in the caller's order and renumbered, gives
+    the tree, D and status worked out in each file."""
+    import test_golden
+    for path in test_golden.CASES:
+        g, seeds, code, tree, total = test_golden.load_case(path)
+        for flags in (st.UPLOAD_KEEP_ORDER, st.UPLOAD_REORDER):
+            with st.Graph(g, 0, stream, flags) as dg:
+                for name, opt in OPTION_SETS.items():
+                    got, t = gpu_code(dg.solve, seeds, opt)
+                    what = f"{os.path.basename(path)} {name} flags={flags}"
+                    assert got == code, f"{what}: status {got}"
+                    if code == st.OK:
+                        assert sorted(t.edges) == tree and t.total == total, what
 
 
 def test_tiny_graphs_all_options(stream):
