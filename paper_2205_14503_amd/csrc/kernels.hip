@@ -239,6 +239,7 @@ DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr
     for (int i = 0; i < UNROLL; i++) {
         const uint32_t nd = (uint32_t)(cand[i] >> 32);
         if (!near[i]) beg[i] = deg[i] = 0;
+        count(P, Lw, EV_PARK, tried[i] && !near[i]);
         if (tried[i] && !near[i]) {  // park until the query's bucket reaches it
             P.dirty[(size_t)slot[i] * n + u[i]] = 1;
             uint32_t *fm = P.far_min + (size_t)R.b * P.nslots + slot[i];
@@ -277,7 +278,6 @@ DEVI void relax_multi(const VorParams &P, const RoundIdx &R, const uint64_t *thr
         }
         count(P, Lw, EV_IMPROVED, tried[i]);
         count(P, Lw, EV_LOCAL, local);
-        count(P, Lw, EV_PARK, tried[i] && !near[i]);
         spill[i] = near[i] && !local;
     }
     // the claims of all steps are in flight together: the returned stamps are used only after the
