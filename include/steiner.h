@@ -158,12 +158,14 @@ int steiner_graph_upload_device(uint32_t n, uint64_t nnz, const void *d_row_ptr,
 
 int steiner_graph_free(steiner_graph *g);
 
-/* Autotuner: times a small set of relaxation settings (bucket width, depth of
- * the wave-local queue, workgroups of a host-stepped pass) on the given sample
- * seed set and keeps the fastest as
- * this graph's defaults for every later call that passes NULL options or zero
- * fields.  Results never depend on the choice.  out (optional) receives the
- * chosen settings.  EINVAL for fewer than 2 distinct seeds. */
+/* Autotuner: times a small set of relaxation settings (bucket width with and
+ * without the deferred expansion of large rows, depth of the wave-local queue,
+ * the light/heavy split, the pred placement, workgroups of a host-stepped pass)
+ * on the given sample seed set and keeps the fastest as this graph's defaults
+ * for every later call that passes NULL options or zero fields.  Results never
+ * depend on the choice.  out (optional) receives the chosen settings (the
+ * split, pred and deferral choices as STEINER_FLAG_* bits).  EINVAL for fewer
+ * than 2 distinct seeds. */
 int steiner_graph_tune(steiner_graph *g, const uint32_t *seeds, uint32_t k, steiner_options *out);
 
 /* Alg. 2 end to end for one seed set (host array of k vertex ids). */
