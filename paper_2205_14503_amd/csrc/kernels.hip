@@ -997,6 +997,7 @@ DEVI bool grid_barrier(Counters *cn, uint32_t nblocks, PassCtl *pass, int *s_abo
     return *s_abort == 0;
 }
 
+template <bool NARROW>
 __global__ void __launch_bounds__(256) k_persistent(VorParams P, uint32_t max_rounds) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     WaveScratch *s_wave = (WaveScratch *)dyn_smem;
@@ -1024,7 +1025,7 @@ __global__ void __launch_bounds__(256) k_persistent(VorParams P, uint32_t max_ro
         const RoundIdx R = round_idx(r);
         const uint32_t cs = min(ld_agent(&P.cnt->s[r % 3u]), P.cap_s);
         const uint32_t cb = min(ld_agent(&P.cnt->b[r % 3u]), P.cap_b);
-        relax_round_body<false>(P, R, s_thr, cs, cb, &s_wave[w], wave_gid, nwaves);
+        relax_round_body<NARROW>(P, R, s_thr, cs, cb, &s_wave[w], wave_gid, nwaves);
         if (blockIdx.x == 0) {
             const uint32_t nb = (r + 1) % 3u;
             for (uint32_t q = threadIdx.x; q < ns; q += blockDim.x) {
@@ -1138,24 +1139,21 @@ __global__ void k_slot_seed(VorParams P, uint32_t slot, const uint32_t *seeds, u
     const uint32_t r = P.pass->round;
     const RoundIdx R = round_idx(r);
     const uint32_t n = P.g.n;
-    for (uint32_t i = threadIdx.x; i < k; i += blockDim.x) {
-        const uint32_t v = seeds[i];
-        P.key[(size_t)slot * n + v] = (uint64_t)i;  // dist 0, seed index i
-        P.aux[(size_t)slot * n + v] = r;
-        const uint32_t deg = P.g.rp[v + 1] - P.g.rp[v];
-        if (deg <= P.small_max) {
-            const uint32_t pos = atomicAdd(&P.cnt->s[r % 3u], 1u);
-            if (pos < P.cap_s) P.items_s[R.cur][pos] = s_item(slot, v);
-            else atomicOr(&P.pass->err, ERR_LIST_OVERFLOW);
-        } else {
-            const uint32_t nch = (deg + P.chunk - 1) / P.chunk;
-            const uint32_t pos = atomicAdd(&P.cnt->b[r % 3u], nch);
-            for (uint32_t c = 0; c < nch; c++) {
-                if (pos + c < P.cap_b) P.items_b[R.cur][pos + c] = b_item(slot, c, v);
-                else { atomicOr(&P.pass->err, ERR_LIST_OVERFLOW); break; }
-            }
+    // wave-uniform loop: the list appends are aggregated per wave (one counter atomic per wave and list)
+    for (uint32_t base = blockIdx.x * blockDim.x; base < k; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        const bool on = i < k;
+        uint32_t v = 0, deg = 0;
+        if (on) {
+            v = seeds[i];
+            P.key[(size_t)slot * n + v] = (uint64_t)i;  // dist 0, seed index i
+            P.aux[(size_t)slot * n + v] = r;
+            deg = P.g.rp[v + 1] - P.g.rp[v];
         }
+        append_s(P, R.cur, r % 3u, on && deg <= P.small_max, s_item(slot, v));
+        append_b(P, R.cur, r % 3u, on && deg > P.small_max, slot, v, deg);
     }
+    if (blockIdx.x != 0) return;
     if (threadIdx.x == 0) {
         P.slot.thr[slot] = P.delta == 0xFFFFFFFFu ? ~0ull : (uint64_t)P.delta;
         P.slot.thr_prev[slot] = 0;
@@ -2156,7 +2154,8 @@ hipError_t launch_slot_start(const VorParams &P, uint32_t slot, const uint32_t *
     if (P.xkey)
         hipLaunchKernelGGL(k_fill<uint64_t>, dim3(fill_grid(P.xchunks)), dim3(256), 0, s,
                            P.xkey + (size_t)slot * P.xchunks, (uint64_t)P.xchunks, KEY_INF);
-    hipLaunchKernelGGL(k_slot_seed, dim3(1), dim3(256), 0, s, P, slot, d_seeds, k);
+    hipLaunchKernelGGL(k_slot_seed, dim3(std::max(1u, std::min((k + 255) / 256, 256u))), dim3(256), 0, s, P, slot,
+                       d_seeds, k);
     return hipGetLastError();
 }
 
@@ -2229,7 +2228,8 @@ int persistent_max_grid(uint32_t block) {
     int dev = 0, per_cu = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent, (int)block, wave_smem(block)) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<false>, (int)block, wave_smem(block)) !=
+        hipSuccess)
         return 0;
     return per_cu * prop.multiProcessorCount;
 }
@@ -2239,7 +2239,10 @@ hipError_t launch_persistent(const VorParams &P, uint32_t grid, uint32_t block, 
     if (P.nslots > PERSIST_SLOTS) return hipErrorInvalidValue;
     VorParams p = P;
     void *args[] = {&p, &max_rounds};
-    return hipLaunchCooperativeKernel((const void *)k_persistent, dim3(grid), dim3(block), args, wave_smem(block), s);
+    // fixed-stride rows, all within the local queue's size limit: the same instance choice as launch_round
+    const bool narrow = P.g.ell && P.g.max_deg <= min(ELL_W, P.small_max);
+    return hipLaunchCooperativeKernel(narrow ? (const void *)k_persistent<true> : (const void *)k_persistent<false>,
+                                      dim3(grid), dim3(block), args, wave_smem(block), s);
 }
 
 hipError_t launch_scan(const ScanParams &S, uint32_t grid, uint32_t block, hipStream_t s) {
