@@ -99,6 +99,30 @@ def _pmc_per_kernel(path: str):
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
+def pmc_table(args):
+    """Mean value per dispatch of every counter in rocprofv3 --pmc counter_collection.csv files, for the
+    relaxation and scan kernels, with the L2 hit rate and the share of wave time spent waiting where the
+    counters for them are present."""
+    import csv
+    acc = {}
+    for path in args.pmc_table:
+        for row in csv.DictReader(open(path)):
+            name = _trace_name(row["Kernel_Name"])
+            acc.setdefault(name, {}).setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+    kernels = [k for k in ("stn::k_round", "stn::k_scan") if k in acc]
+    counters = sorted({c for k in kernels for c in acc[k]})
+    print("| kernel | dispatches | " + " | ".join(counters) + " | L2 hit rate | waiting share of wave cycles |")
+    print("|---|---|" + "---|" * (len(counters) + 2))
+    for k in kernels:
+        m = {c: sum(v) / len(v) for c, v in acc[k].items()}
+        hit = m.get("TCC_HIT_sum"), m.get("TCC_MISS_sum")
+        rate = f"{hit[0] / (hit[0] + hit[1]):.3f}" if None not in hit and hit[0] + hit[1] else ""
+        wait = m.get("SQ_WAIT_INST_ANY"), m.get("SQ_WAVE_CYCLES")
+        share = f"{wait[0] / wait[1]:.3f}" if None not in wait and wait[1] else ""
+        n = max(len(v) for v in acc[k].values())
+        print(f"| {k} | {n} | " + " | ".join(f"{m.get(c, 0):.4g}" for c in counters) + f" | {rate} | {share} |")
+
+
 def _config_key(delta, local, split=None, grid=0, defer=False) -> str:
     key = f"delta={int(delta)},local_iters={int(local)},split={split or 0}"
     return key + (f",grid={int(grid)}" if grid else "") + (",defer=1" if defer else "")
@@ -438,6 +462,8 @@ def main():
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the workload's entry of profiles/traffic.json from rocprofv3 counter runs "
                          "(with the --delta and --local those runs used)")
+    ap.add_argument("--pmc-table", nargs="+", metavar="COUNTER_CSV",
+                    help="per-dispatch means of rocprofv3 --pmc counters for the relaxation and scan kernels")
     ap.add_argument("--busy-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
                     help="GPU-busy time per phase of a batching or serving run under rocprofv3")
     ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
@@ -451,6 +477,9 @@ def main():
         return
     if args.busy_summary:
         busy_summary(args)
+        return
+    if args.pmc_table:
+        pmc_table(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path.",
