@@ -177,15 +177,15 @@ Options resolve_options(const steiner_graph *g, const steiner_options *o) {
     if (r.chunk < 64) r.chunk = 64;
     while ((g->max_deg + r.chunk - 1) / r.chunk >= (1ull << CHUNK_BITS)) r.chunk *= 2;  // chunk index field
     // host-stepped: as many workgroups as are resident at once (the round kernel's occupancy);
-    // persistent: one per CU (co-resident, as its grid barrier needs; two per CU ran grid2048 at 27 ms against
-    // 9.4 and RMAT-22 at 26 against 21)
+    // persistent: one per CU on fixed-stride graphs and two elsewhere (co-resident, as its grid barrier needs;
+    // measured: grid2048 5.2 / 7.8 ms and RMAT-22 18.7 / 14.0 ms at one / two per CU)
     // passes of the host-stepped driver use the tuned count (a latency-bound graph often runs faster on
     // fewer workgroups), batches at least half the resident count (their frontier is larger); the server
     // keeps every resident one
     const bool given = r.grid != 0;
     if (!given) {
         if (r.driver == 2) {
-            r.grid = (uint32_t)std::max(1, g->cu_count);
+            r.grid = (uint32_t)std::max(1, g->cu_count) * (g->d_ell ? 1u : 2u);
         } else {
             const int resident = round_max_grid(r.block);
             r.grid = resident > 0 ? (uint32_t)resident : (uint32_t)std::max(1, g->cu_count) * 4u;

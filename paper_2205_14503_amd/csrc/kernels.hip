@@ -964,12 +964,15 @@ __global__ void __launch_bounds__(256) k_round(VorParams P) {
 
 // ---------------------------------------------------------------- persistent
 
-// Sense-counting grid barrier for a cooperative launch.  Gives up after a
-// bounded spin (then every workgroup leaves the kernel).
+// Sense-counting grid barrier for a cooperative launch.  The arrival's
+// acquire-release atomic publishes the workgroup's writes; the wait polls with
+// relaxed loads and acquires once when it ends (an acquiring load in the loop
+// would invalidate the L2 on every poll, slowing every other workgroup in
+// proportion to the number waiting).  Gives up after a bounded spin (then
+// every workgroup leaves the kernel).
 DEVI bool grid_barrier(Counters *cn, uint32_t nblocks, PassCtl *pass, int *s_abort) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
         const uint32_t g = __hip_atomic_load(&cn->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t arrived =
             __hip_atomic_fetch_add(&cn->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -979,7 +982,7 @@ DEVI bool grid_barrier(Counters *cn, uint32_t nblocks, PassCtl *pass, int *s_abo
             __hip_atomic_fetch_add(&cn->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             uint32_t spins = 0;
-            while (__hip_atomic_load(&cn->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (__hip_atomic_load(&cn->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(2);
                 if (++spins > (1u << 25) ||
                     __hip_atomic_load(&cn->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -990,7 +993,7 @@ DEVI bool grid_barrier(Counters *cn, uint32_t nblocks, PassCtl *pass, int *s_abo
                 }
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_abort = ab;
     }
     __syncthreads();
